@@ -1,0 +1,29 @@
+"""Oracle: a plain, slow, FP64 CPU implementation of the central-flux DG
+Maxwell solver, written from the paper's statement of the method.
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it.  The product
+(``paper_1104_4208_amd``) never imports or calls it, and it shares no code
+with the product: its Jacobi polynomials, quadrature, basis, geometry,
+neighbour search and operators are written here independently.
+
+Contents
+  jacobi  -- Jacobi polynomials (three-term recurrence), Gauss-Jacobi rules
+  basis   -- orthonormal Dubiner basis on the reference tetrahedron (Section 4.2.2)
+  dg      -- mesh geometry, L2 projection, strong-form H / weak-form E central-flux
+             right-hand sides, symplectic Euler (Section 3), energies, power
+             iteration for the time-step bound, dense operator assembly.
+
+Pins (tests/test_oracle_*.py) tie each function to something other than
+itself: closed-form norms, orthogonality, integration by parts, exact
+polynomial reproduction of curl, skew-symmetry of the semi-discrete system,
+exact conservation of the leapfrog invariant, the scalar stability
+threshold, and h-convergence to the exact PEC cube eigenmodes.
+
+Parity unpinned: the paper's own experiments (the spherical resonator of
+Section 2.2 and the timings of Section 3.5) cannot be reproduced here: the
+meshes and the reference data are not available.
+"""
+from .basis import eval_basis, mode_list, num_modes, tet_quadrature, triangle_quadrature  # noqa: F401
+from .dg import Mesh, Solver, build_mesh  # noqa: F401
+from .jacobi import djacobi, gauss_jacobi, jacobi  # noqa: F401
