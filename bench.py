@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark: FP32 DG Maxwell leapfrog steps on one MI355X.
+
+Workload (the p = 6 precision workload): the unit-cube PEC cavity split into
+32^3 cells x 6 Kuhn tetrahedra = 196,608 tets, vertices jittered by U(+-0.1 h)
+(seed 3), eps drawn from {1, 4} per element, mu = 1, order p = 6 (84 modes per
+component, 99,090,432 DOFs), initial E = sum of three cavity modes with
+N(0,1) amplitudes, H = 0, dt = 0.5 * 2 / sqrt(rho) from the library's power
+iteration.  A step is one full symplectic-Euler step (H phase + E phase) over
+the whole mesh.  Inputs are resident in HBM when the timed region starts.
+
+    python bench.py [--gpus 1] [--steps 500] [--warmup 20]
+
+Prints one JSON line.  value = 6 N K steps / wall time (DOF-updates/s).
+roofline: the dominant kernel is the generated phase kernel; its algorithmic
+traffic is 36 N + 40 bytes per element per launch (read the differentiated
+field, read and write the updated field, 24 B of metric and 16 B of neighbour
+codes); its average duration is measured live with HIP events on the stream it
+is launched on (difference of a long and a one-step run, so the frame
+conversions at the ends cancel).  cpu_baseline: the FP64 oracle timed on a
+bounded sample of the same workload (smaller cube, same order and recipe).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(workload="pec_cube_cavity_kuhn32_p6_fp32", cells=32, tets=196608, p=6, modes=84,
+                dofs=99090432, jitter=0.1, eps=[1, 4], steps_in_config=500, init="three cavity modes, seed 3")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_p6_cube32_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def build_inputs():
+    import synth
+    from paper_1104_4208_amd.project import project_covariant
+
+    w = synth.WORKLOADS["cube32_p6_f32"]
+    d = synth.build_workload(w)
+    E0 = project_covariant(d["verts"], d["tets"], w.p, d["field"].E)
+    return w, d, E0
+
+
+def cpu_baseline(target_seconds: float):
+    """FP64 oracle on a bounded sample: the same recipe on a 4^3-cell cube (384 tets),
+    p = 6, as many steps as fit in about target_seconds."""
+    import oracle
+    import synth
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    rng = np.random.default_rng(3)
+    verts, tets = synth.kuhn_mesh(4, 0.1, rng)
+    K = tets.shape[0]
+    eps = rng.choice([1.0, 4.0], size=K)
+    s = oracle.Solver(oracle.build_mesh(verts, np.sort(tets, axis=1)), 6, eps)
+    fld = synth.three_mode_sum(rng)
+    E = s.project(fld.E)
+    H = np.zeros_like(E)
+    dt = 1e-3
+    E, H = s.step(E, H, dt, 1)  # warm caches
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < target_seconds or n < 2:
+        E, H = s.step(E, H, dt, 1)
+        n += 1
+    el = time.perf_counter() - t0
+    rate = 6 * s.N * K * n / el
+    return {"value": rate, "unit": "DOF-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 oracle, 4^3 x 6 = {K} jittered tets, p=6, eps in {{1,4}}, {n} steps in {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1104_4208_amd as P
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    w, d, E0 = build_inputs()
+    K, p = d["tets"].shape[0], w.p
+    N = P.num_modes(p)
+    m = P.Mesh(d["verts"], d["tets"]).set_order(p).set_material(d["eps"], d["mu"])
+    dt, rho = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
+    E = torch.tensor(np.ascontiguousarray(E0), dtype=torch.float32, device="cuda").contiguous()
+    H = torch.zeros_like(E)
+    torch.cuda.synchronize()
+    W0, Q0 = m.energy(E, H, dt=dt)
+    m.step(E, H, dt, a.warmup)
+    stream = torch.cuda.current_stream()
+
+    def timed(nsteps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        m.step(E, H, dt, nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one = min(timed(1) for _ in range(3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = timed(a.steps)
+    wall = time.perf_counter() - t0
+    W1, Q1 = m.energy(E, H, dt=dt)
+    steps_done = a.warmup + 3 + a.steps
+    phase_s = (ev - one) / (2 * (a.steps - 1)) if a.steps > 1 else ev / 2
+    bytes_launch = K * (36 * N + 40)
+    achieved = bytes_launch / phase_s / 1e9
+    value = 6 * N * K * a.steps / wall
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": "DOF-updates/sec & %HBM roofline at p=6 (FP32 vs FP64 oracle err); serving p50/p99",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(WORKLOAD, dt=dt, rho=rho),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "dgm_phase_p6<float>", "phase_us": phase_s * 1e6, "bytes_per_launch": bytes_launch},
+        "energy": {"W0": W0, "Q0": Q0, "Q_end": Q1, "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps_done},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * dgmax.h -- C-ABI of the MI355X discontinuous Galerkin Maxwell curl engine.
+ *
+ * The library applies the central-flux DG curl operator of the loss-free
+ * time-domain Maxwell equations on affine tetrahedra (Koutschan, Lehrenfeld,
+ * Schoeberl, arxiv 1104.4208):
+ *     eps dE/dt =  curl H,   mu dH/dt = -curl E                  (Section 2)
+ * discretised with piecewise polynomials of degree p in an L2-orthonormal
+ * Dubiner basis (Sections 3.1 and 4.2.2), the covariant map (Section 3.2.1),
+ * element-local mass inverses (Section 3.3.1) and the central flux
+ * (Section 2.1, eq. semidiscrete), advanced by symplectic Euler / leapfrog
+ * with H updated first (Section 3).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status: DGM_OK (0) or a negative DGM_ERR_*
+ *    code; dgm_last_error() then returns a thread-local message.  No C++
+ *    exception crosses this interface.
+ *  - Field arrays (E, H, dE, dH, H_next) are caller-owned DEVICE buffers
+ *    shaped (3, N, K), contiguous, element index fastest, of type float
+ *    (dtype DGM_F32) or double (DGM_F64), with N = dgm_num_modes(p) and K the
+ *    number of tetrahedra.  Entry [c][m][e] is component c of the reference
+ *    covariant coefficient of volume mode m on element e: the physical field
+ *    on e is F_e^{-T} sum_m Ehat_m phi_m(xhat), where F_e = [v1-v0, v2-v0,
+ *    v3-v0] is built from the element's vertices sorted by ascending global
+ *    id, and the mode order is the one reported by dgm_mode_index.
+ *  - Work is enqueued on the caller's HIP stream; calls that return host
+ *    values (dgm_energy, dgm_estimate_dt) synchronise that stream.
+ *  - The library never frees caller memory.  It owns the mesh handle and the
+ *    device arrays it allocates for it (geometry, neighbour codes, scratch).
+ *  - Walls: every face without a neighbour is a perfect electric conductor
+ *    (ghost states E_nb = -E, H_nb = H).
+ *  - Calls on one mesh handle must not overlap in time (they share scratch).
+ */
+#ifndef DGMAX_H
+#define DGMAX_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgm_mesh dgm_mesh;
+
+enum { DGM_F32 = 0, DGM_F64 = 1 };
+
+enum {
+  DGM_OK = 0,
+  DGM_ERR_ARG = -1,              /* null pointer, bad size, order out of range */
+  DGM_ERR_MESH_DEGENERATE = -2,  /* |det F| < 1e-12 h^3 or repeated vertex */
+  DGM_ERR_MESH_NONMANIFOLD = -3, /* a face shared by more than two tetrahedra */
+  DGM_ERR_MATERIAL = -4,         /* eps or mu not strictly positive / not finite */
+  DGM_ERR_OOM = -5,              /* device allocation failed */
+  DGM_ERR_HIP = -6,              /* a HIP runtime call failed (message has the HIP error) */
+  DGM_ERR_UNSTABLE = -7,         /* non-finite energy detected */
+  DGM_ERR_STATE = -8             /* order not set */
+};
+
+/* Thread-local description of the last error returned on this thread. */
+const char* dgm_last_error(void);
+
+/* Number of volume modes (p+1)(p+2)(p+3)/6 and face modes (p+1)(p+2)/2. */
+int dgm_num_modes(int p);
+int dgm_num_face_modes(int p);
+/* Highest order compiled into this library for dtype (DGM_F32 / DGM_F64). */
+int dgm_max_order(int dtype);
+
+/* Mode m (0 <= m < N) of order p is phi_{i,j,k} of Section 4.2.2 scaled to unit
+ * norm: i indexes the innermost (z) Legendre factor, j the y factor, k the x
+ * factor.  Modes are ordered by total degree, then i, then j. */
+int dgm_mode_index(int p, int m, int* i, int* j, int* k);
+
+/* Build a mesh from host arrays (copied): verts[nv][3] (FP64), tets[nt][4]
+ * (vertex ids in [0, nv)).  Vertices of each tetrahedron are sorted by
+ * ascending id, so both sides of a face parametrise it identically; the
+ * neighbour map is built from shared vertex triples (Section 3, locality of
+ * the DG curl).  Errors: DGM_ERR_ARG, DGM_ERR_MESH_DEGENERATE,
+ * DGM_ERR_MESH_NONMANIFOLD, DGM_ERR_OOM, DGM_ERR_HIP.  Material defaults to
+ * eps = mu = 1 and the order must be set before any field operation. */
+int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_t nt, dgm_mesh** out);
+
+/* Release the handle and every device array the library allocated for it. */
+int dgm_destroy(dgm_mesh* mesh);
+
+/* Number of tetrahedra of the mesh. */
+int dgm_num_elements(const dgm_mesh* mesh, int64_t* K);
+
+/* Select the polynomial order p (1 <= p <= dgm_max_order(dtype) at use time). */
+int dgm_set_order(dgm_mesh* mesh, int p);
+
+/* Per-element piecewise-constant permittivity and permeability (host arrays of
+ * length K, each > 0; NULL means 1).  Folds the flat-element mass inverse
+ * |det F| eps F^{-1} F^{-T} (Section 3.3.1, eq. massintegral) into per-element
+ * factors.  Errors: DGM_ERR_MATERIAL, DGM_ERR_HIP. */
+int dgm_set_material(dgm_mesh* mesh, const double* eps, const double* mu);
+
+/* Semi-discrete right-hand side (Section 2.1, eq. semidiscrete):
+ *     dE = -M_eps^{-1} C^T H  (= eps^{-1} curl_h H),
+ *     dH =  M_mu^{-1} C E     (= -mu^{-1} curl_h E),
+ * in the covariant layout above.  Either output may be NULL (then the matching
+ * input may be NULL too).  Outputs must not alias inputs. */
+int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void* dE, void* dH,
+                   hipStream_t stream);
+
+/* nsteps symplectic Euler steps in place (Section 3):
+ *     H <- H + dt M_mu^{-1} C E,   E <- E - dt M_eps^{-1} C^T H.
+ * dt is the caller's (see dgm_estimate_dt); nsteps >= 0. */
+int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
+
+/* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),
+ * out[1] = Q = 1/2 (E, M_eps E) + 1/2 (H, M_mu H_next), the quantity the
+ * H-first symplectic Euler step conserves exactly.  H_next is the H of the next
+ * step; if NULL it is computed internally as H + dt dH(E).  Returns
+ * DGM_ERR_UNSTABLE if W or Q is not finite (out is still written). */
+int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const void* H_next, double dt,
+               double out[2], hipStream_t stream);
+
+/* Time step from the stability bound of Section 3: power iteration (iters
+ * steps, start vector from SplitMix64(seed) over the (3,N,K) layout, mapped to
+ * [-1,1)) estimates rho = rho(M_mu^{-1/2} C M_eps^{-1} C^T M_mu^{-1/2}); the
+ * result is dt = cfl * 2 / sqrt(rho) (the printed bound lacks the square root;
+ * leapfrog is stable iff dt <= 2/sqrt(rho)).  rho_out may be NULL.  Runs in
+ * FP64 on the device; synchronises the stream. */
+int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
+                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGMAX_H */

@@ -1,0 +1,651 @@
+// Host side of the DG Maxwell curl engine: FP64 geometry preprocessing, the
+// C-ABI declared in include/dgmax.h, and the small support kernels (frame
+// conversion, FP64 energy reduction).  The per-order phase kernels are
+// generated (gen/emit.py) and compiled in their own translation units.
+//
+// Storage frames.  The ABI exchanges reference covariant coefficients uhat
+// (physical field F^{-T} uhat, Section 3.2.1).  Inside dgm_step the state is
+// kept in the frame S = det(A) A^{-T} K^{-1} uhat, where K = F^T F / (eps J) is
+// the flat-element mass inverse of Section 3.3.1 (signed J carries the sign of
+// the covariant curl identity) and A holds the three derivative directions.
+// In that frame the mass inverse moves to the input side (w = M S with
+// M = A K A^T / det A symmetric) and the update of each component is
+// independent of the other two, which lets the phase kernel finish one
+// component at a time.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dgmax.h"
+#include "launch.h"
+#include "generated/frame.inc"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? DGM_ERR_OOM : DGM_ERR_HIP,                \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+int num_modes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// ---------------------------------------------------------------- kernels
+// X_m <- P X_m for every mode m of every element, P = (Minv A) (to the stored
+// frame) or (Ainv M) (back to covariant).  M, Minv are symmetric, stored (6,K).
+template <typename R>
+__global__ void convert_kernel(R* __restrict__ X, const R* __restrict__ Msym, int N, int K, int to_stored,
+                               double a00, double a01, double a02, double a10, double a11, double a12,
+                               double a20, double a21, double a22) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K) return;
+  const size_t Ks = (size_t)K;
+  const double s00 = Msym[0 * Ks + e], s01 = Msym[1 * Ks + e], s02 = Msym[2 * Ks + e];
+  const double s11 = Msym[3 * Ks + e], s12 = Msym[4 * Ks + e], s22 = Msym[5 * Ks + e];
+  const double S[3][3] = {{s00, s01, s02}, {s01, s11, s12}, {s02, s12, s22}};
+  const double C[3][3] = {{a00, a01, a02}, {a10, a11, a12}, {a20, a21, a22}};
+  double P[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      for (int q = 0; q < 3; ++q) acc += to_stored ? S[r][q] * C[q][c] : C[r][q] * S[q][c];
+      P[r][c] = acc;
+    }
+  for (int m = 0; m < N; ++m) {
+    R* x0 = X + ((size_t)(0 * N + m)) * Ks + e;
+    R* x1 = X + ((size_t)(1 * N + m)) * Ks + e;
+    R* x2 = X + ((size_t)(2 * N + m)) * Ks + e;
+    const double v0 = *x0, v1 = *x1, v2 = *x2;
+    *x0 = (R)(P[0][0] * v0 + P[0][1] * v1 + P[0][2] * v2);
+    *x1 = (R)(P[1][0] * v0 + P[1][1] * v1 + P[1][2] * v2);
+    *x2 = (R)(P[2][0] * v0 + P[2][1] * v1 + P[2][2] * v2);
+  }
+}
+
+template <typename R>
+__global__ void fill_kernel(R* __restrict__ X, size_t n, R v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[i] = v;
+}
+
+// Y <- X + a * Y  (used to form H_next = H + dt dH in place of dH)
+template <typename R>
+__global__ void xpay_kernel(R* __restrict__ Y, const R* __restrict__ X, size_t n, double a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Y[i] = (R)((double)X[i] + a * (double)Y[i]);
+}
+
+// Mass-weighted dot products in FP64: out[b] = sum over the block's elements of
+// sum_m A_m^T G_e B_m, with G = |J| eps F^{-1} F^{-T} symmetric (6,K).
+// Deterministic: fixed block partition, fixed tree, separate final pass.
+constexpr int kRedThreads = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) mdot_partial_kernel(const R* __restrict__ A, const R* __restrict__ B,
+                                                                   const double* __restrict__ G, int N, int K,
+                                                                   double* __restrict__ partial) {
+  __shared__ double red[kRedThreads];
+  const int e = blockIdx.x * kRedThreads + threadIdx.x;
+  double acc = 0.0;
+  if (e < K) {
+    const size_t Ks = (size_t)K;
+    const double g00 = G[0 * Ks + e], g01 = G[1 * Ks + e], g02 = G[2 * Ks + e];
+    const double g11 = G[3 * Ks + e], g12 = G[4 * Ks + e], g22 = G[5 * Ks + e];
+    for (int m = 0; m < N; ++m) {
+      const double a0 = A[(size_t)(0 * N + m) * Ks + e], a1 = A[(size_t)(1 * N + m) * Ks + e],
+                   a2 = A[(size_t)(2 * N + m) * Ks + e];
+      const double b0 = B[(size_t)(0 * N + m) * Ks + e], b1 = B[(size_t)(1 * N + m) * Ks + e],
+                   b2 = B[(size_t)(2 * N + m) * Ks + e];
+      acc += a0 * (g00 * b0 + g01 * b1 + g02 * b2) + a1 * (g01 * b0 + g11 * b1 + g12 * b2) +
+             a2 * (g02 * b0 + g12 * b1 + g22 * b2);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) final_sum_kernel(const double* __restrict__ partial, int n,
+                                                                double* __restrict__ out) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kRedThreads) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) mapped to [-1, 1): start vector of the
+// power iteration, identical to the host reference generator.
+__global__ void splitmix_fill_kernel(double* __restrict__ X, size_t n, unsigned long long seed) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  X[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+__global__ void scale_kernel(double* __restrict__ X, size_t n, const double* __restrict__ d) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[i] = -X[i] / sqrt(*d);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- mesh
+struct dgm_mesh {
+  int64_t K = 0;
+  int p = 0;
+  std::vector<double> F;   // (K,9) row-major 3x3, columns v1-v0, v2-v0, v3-v0 (sorted vertices)
+  std::vector<double> J;   // signed det F
+  std::vector<int> nbr;    // (4,K)
+  // device
+  int* d_nbr = nullptr;
+  float* d_M32[2] = {nullptr, nullptr};      // E, H: w = M S
+  double* d_M64[2] = {nullptr, nullptr};
+  float* d_Minv32[2] = {nullptr, nullptr};   // S = Minv A uhat
+  double* d_Minv64[2] = {nullptr, nullptr};
+  double* d_G[2] = {nullptr, nullptr};       // |J| eps F^-1 F^-T (energy)
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  double* d_partial = nullptr;
+  int partial_n = 0;
+};
+
+namespace {
+
+int ensure_scratch(dgm_mesh* m, size_t bytes) {
+  if (m->scratch_bytes >= bytes) return DGM_OK;
+  if (m->d_scratch) HIP_TRY(hipFree(m->d_scratch));
+  m->d_scratch = nullptr;
+  m->scratch_bytes = 0;
+  HIP_TRY(hipMalloc(&m->d_scratch, bytes));
+  m->scratch_bytes = bytes;
+  return DGM_OK;
+}
+
+void sym6(const double S[3][3], double* out6) {
+  out6[0] = S[0][0]; out6[1] = S[0][1]; out6[2] = S[0][2];
+  out6[3] = S[1][1]; out6[4] = S[1][2]; out6[5] = S[2][2];
+}
+
+bool inv3(const double a[3][3], double r[3][3]) {
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  if (det == 0.0 || !std::isfinite(det)) return false;
+  r[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / det;
+  r[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / det;
+  r[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / det;
+  r[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) / det;
+  r[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / det;
+  r[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / det;
+  r[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) / det;
+  r[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / det;
+  r[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
+  return true;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src) {
+  if (!*dst) HIP_TRY(hipMalloc(dst, src.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DGM_OK;
+}
+
+int material_impl(dgm_mesh* m, const double* eps, const double* mu) {
+  const int64_t K = m->K;
+  const double(*A)[3] = reinterpret_cast<const double(*)[3]>(kFrameA);
+  for (int fld = 0; fld < 2; ++fld) {
+    const double* mat = fld == 0 ? eps : mu;
+    std::vector<double> M64(6 * K), Minv64(6 * K), G(6 * K);
+    for (int64_t e = 0; e < K; ++e) {
+      const double c = mat ? mat[e] : 1.0;
+      if (!(c > 0.0) || !std::isfinite(c))
+        return fail(DGM_ERR_MATERIAL, "material value must be finite and > 0 (element " + std::to_string(e) + ")");
+      double Fm[3][3], FtF[3][3], Fi[3][3], FiFiT[3][3], Km[3][3], AK[3][3], Mm[3][3], Mi[3][3];
+      std::memcpy(Fm, &m->F[9 * e], sizeof(Fm));
+      const double Je = m->J[e];
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += Fm[q][r] * Fm[q][s];
+          FtF[r][s] = acc;
+          Km[r][s] = acc / (c * Je);  // flat-element mass inverse, sign of J included
+        }
+      inv3(Fm, Fi);
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += Fi[r][q] * Fi[s][q];
+          FiFiT[r][s] = std::fabs(Je) * c * acc;
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += A[r][q] * Km[q][s];
+          AK[r][s] = acc;
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+          double acc = 0.0;
+          for (int q = 0; q < 3; ++q) acc += AK[r][q] * A[s][q];
+          Mm[r][s] = acc / kFrameDetA;
+        }
+      // symmetrise against rounding before inverting
+      for (int r = 0; r < 3; ++r)
+        for (int s = r + 1; s < 3; ++s) Mm[r][s] = Mm[s][r] = 0.5 * (Mm[r][s] + Mm[s][r]);
+      if (!inv3(Mm, Mi)) return fail(DGM_ERR_MESH_DEGENERATE, "singular element metric");
+      double o6[6];
+      sym6(Mm, o6);
+      for (int q = 0; q < 6; ++q) M64[q * K + e] = o6[q];
+      sym6(Mi, o6);
+      for (int q = 0; q < 6; ++q) Minv64[q * K + e] = o6[q];
+      sym6(FiFiT, o6);
+      for (int q = 0; q < 6; ++q) G[q * K + e] = o6[q];
+      (void)FtF;
+    }
+    std::vector<float> M32(M64.begin(), M64.end()), Minv32(Minv64.begin(), Minv64.end());
+    int rc;
+    if ((rc = upload(&m->d_M64[fld], M64))) return rc;
+    if ((rc = upload(&m->d_Minv64[fld], Minv64))) return rc;
+    if ((rc = upload(&m->d_M32[fld], M32))) return rc;
+    if ((rc = upload(&m->d_Minv32[fld], Minv32))) return rc;
+    if ((rc = upload(&m->d_G[fld], G))) return rc;
+  }
+  return DGM_OK;
+}
+
+template <typename R> R* Mdev(dgm_mesh* m, int fld);
+template <> float* Mdev<float>(dgm_mesh* m, int fld) { return m->d_M32[fld]; }
+template <> double* Mdev<double>(dgm_mesh* m, int fld) { return m->d_M64[fld]; }
+template <typename R> R* Minvdev(dgm_mesh* m, int fld);
+template <> float* Minvdev<float>(dgm_mesh* m, int fld) { return m->d_Minv32[fld]; }
+template <> double* Minvdev<double>(dgm_mesh* m, int fld) { return m->d_Minv64[fld]; }
+
+hipError_t phase(const PhaseArgs<float>& a, int p) { return kPhaseF32[p](a); }
+hipError_t phase(const PhaseArgs<double>& a, int p) { return kPhaseF64[p](a); }
+
+int check_order(dgm_mesh* m, int dtype) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  if (dtype != DGM_F32 && dtype != DGM_F64) return fail(DGM_ERR_ARG, "dtype must be DGM_F32 or DGM_F64");
+  if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
+  const int pmax = dtype == DGM_F32 ? DGM_MAX_ORDER_F32 : DGM_MAX_ORDER_F64;
+  if (m->p > pmax)
+    return fail(DGM_ERR_ARG, "order " + std::to_string(m->p) + " not compiled for this dtype (max " +
+                                 std::to_string(pmax) + ")");
+  return DGM_OK;
+}
+
+template <typename R>
+int convert(dgm_mesh* m, R* X, int fld, bool to_stored, hipStream_t s) {
+  const double* C = to_stored ? kFrameA : kFrameAinv;
+  const R* Msym = to_stored ? Minvdev<R>(m, fld) : Mdev<R>(m, fld);
+  const int threads = 256;
+  hipLaunchKernelGGL(convert_kernel<R>, dim3((unsigned)((m->K + threads - 1) / threads)), dim3(threads), 0, s, X, Msym,
+                     num_modes(m->p), (int)m->K, to_stored ? 1 : 0, C[0], C[1], C[2], C[3], C[4], C[5], C[6], C[7],
+                     C[8]);
+  HIP_TRY(hipGetLastError());
+  return DGM_OK;
+}
+
+template <typename R>
+int fill(R* X, size_t n, R v, hipStream_t s) {
+  const int threads = 256;
+  hipLaunchKernelGGL(fill_kernel<R>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, X, n, v);
+  HIP_TRY(hipGetLastError());
+  return DGM_OK;
+}
+
+// One phase on stored-frame data.  fld_u: 0 if U is E (H update), 1 if U is H.
+template <typename R>
+int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, hipStream_t s) {
+  PhaseArgs<R> a;
+  a.U = U;
+  a.V = V;
+  a.MU = Mdev<R>(m, fld_u);
+  a.nbr = m->d_nbr;
+  a.sdt = (R)sdt;
+  a.wall = fld_u == 0 ? (R)-1 : (R)1;
+  a.K = (int)m->K;
+  a.blocks = (int)((m->K + 63) / 64);
+  a.stream = s;
+  HIP_TRY(phase(a, m->p));
+  return DGM_OK;
+}
+
+// Covariant rate: out = d/dt of the other field from the covariant input `in`.
+// fld_u = 0: in = E, out = dH;  fld_u = 1: in = H, out = dE.
+template <typename R>
+int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s) {
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  int rc;
+  if ((rc = ensure_scratch(m, n * sizeof(R)))) return rc;
+  R* tmp = static_cast<R*>(m->d_scratch);
+  HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(R), hipMemcpyDeviceToDevice, s));
+  if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
+  if ((rc = fill<R>(out, n, (R)0, s))) return rc;
+  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, s))) return rc;
+  return convert<R>(m, out, 1 - fld_u, false, s);
+}
+
+template <typename R>
+int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s) {
+  int rc;
+  if (nsteps == 0) return DGM_OK;
+  if ((rc = convert<R>(m, E, 0, true, s))) return rc;
+  if ((rc = convert<R>(m, H, 1, true, s))) return rc;
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if ((rc = run_phase<R>(m, E, H, 0, -dt, s))) return rc;  // H update from curl E
+    if ((rc = run_phase<R>(m, H, E, 1, dt, s))) return rc;   // E update from curl H
+  }
+  if ((rc = convert<R>(m, E, 0, false, s))) return rc;
+  return convert<R>(m, H, 1, false, s);
+}
+
+template <typename R>
+int mdot(dgm_mesh* m, const R* A, const R* B, int fld, double* d_out, hipStream_t s) {
+  const int nb = (int)((m->K + kRedThreads - 1) / kRedThreads);
+  if (m->partial_n < nb) {
+    if (m->d_partial) HIP_TRY(hipFree(m->d_partial));
+    m->d_partial = nullptr;
+    HIP_TRY(hipMalloc(&m->d_partial, nb * sizeof(double)));
+    m->partial_n = nb;
+  }
+  hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, A, B, m->d_G[fld], num_modes(m->p),
+                     (int)m->K, m->d_partial);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_out);
+  HIP_TRY(hipGetLastError());
+  return DGM_OK;
+}
+
+template <typename R>
+int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, double out[2], hipStream_t s) {
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  int rc;
+  double* d_res = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&d_res), 4 * sizeof(double), s));
+  const R* Hq = Hn;
+  R* hn_buf = nullptr;
+  if (!Hq) {
+    // H_next = H + dt dH(E); the rate uses the first half of the scratch, H_next the second
+    if ((rc = ensure_scratch(m, 2 * n * sizeof(R)))) return rc;
+    hn_buf = static_cast<R*>(m->d_scratch) + n;
+    if ((rc = rate_impl<R>(m, E, hn_buf, 0, s))) return rc;
+    const int threads = 256;
+    hipLaunchKernelGGL(xpay_kernel<R>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, hn_buf, H,
+                       n, dt);
+    HIP_TRY(hipGetLastError());
+    Hq = hn_buf;
+  }
+  if ((rc = mdot<R>(m, E, E, 0, d_res + 0, s))) return rc;
+  if ((rc = mdot<R>(m, H, H, 1, d_res + 1, s))) return rc;
+  if ((rc = mdot<R>(m, H, Hq, 1, d_res + 2, s))) return rc;
+  double h[4];
+  HIP_TRY(hipMemcpyAsync(h, d_res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipFreeAsync(d_res, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out[0] = 0.5 * h[0] + 0.5 * h[1];
+  out[1] = 0.5 * h[0] + 0.5 * h[2];
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(DGM_ERR_UNSTABLE, "non-finite energy");
+  return DGM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C-ABI
+extern "C" {
+
+const char* dgm_last_error(void) { return g_err.c_str(); }
+
+int dgm_num_modes(int p) { return p < 0 ? 0 : num_modes(p); }
+int dgm_num_face_modes(int p) { return p < 0 ? 0 : (p + 1) * (p + 2) / 2; }
+int dgm_max_order(int dtype) { return dtype == DGM_F64 ? DGM_MAX_ORDER_F64 : DGM_MAX_ORDER_F32; }
+
+int dgm_mode_index(int p, int m, int* i, int* j, int* k) {
+  if (p < 0 || m < 0 || m >= num_modes(p) || !i || !j || !k) return fail(DGM_ERR_ARG, "mode index out of range");
+  int r = 0;
+  for (int n = 0; n <= p; ++n)
+    for (int a = 0; a <= n; ++a)
+      for (int b = 0; b <= n - a; ++b, ++r)
+        if (r == m) {
+          *i = a;
+          *j = b;
+          *k = n - a - b;
+          return DGM_OK;
+        }
+  return fail(DGM_ERR_ARG, "mode index out of range");
+}
+
+int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_t nt, dgm_mesh** out) {
+  if (!verts || !tets || !out || nv < 4 || nt < 1) return fail(DGM_ERR_ARG, "bad mesh arguments");
+  if (nt > (int64_t(1) << 28)) return fail(DGM_ERR_ARG, "too many elements");
+  *out = nullptr;
+  auto* m = new dgm_mesh();
+  m->K = nt;
+  m->F.resize(9 * nt);
+  m->J.resize(nt);
+  std::vector<int64_t> sorted(4 * nt);
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t v[4];
+    for (int q = 0; q < 4; ++q) {
+      v[q] = tets[4 * e + q];
+      if (v[q] < 0 || v[q] >= nv) {
+        delete m;
+        return fail(DGM_ERR_ARG, "vertex id out of range in element " + std::to_string(e));
+      }
+    }
+    std::sort(v, v + 4);
+    if (v[0] == v[1] || v[1] == v[2] || v[2] == v[3]) {
+      delete m;
+      return fail(DGM_ERR_MESH_DEGENERATE, "repeated vertex in element " + std::to_string(e));
+    }
+    double P[4][3], h = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      sorted[4 * e + q] = v[q];
+      for (int d = 0; d < 3; ++d) P[q][d] = verts[3 * v[q] + d];
+    }
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        double l2 = 0.0;
+        for (int d = 0; d < 3; ++d) l2 += (P[a][d] - P[b][d]) * (P[a][d] - P[b][d]);
+        h = std::max(h, std::sqrt(l2));
+      }
+    double Fm[3][3];
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c) Fm[d][c] = P[c + 1][d] - P[0][d];
+    const double J = Fm[0][0] * (Fm[1][1] * Fm[2][2] - Fm[1][2] * Fm[2][1]) -
+                     Fm[0][1] * (Fm[1][0] * Fm[2][2] - Fm[1][2] * Fm[2][0]) +
+                     Fm[0][2] * (Fm[1][0] * Fm[2][1] - Fm[1][1] * Fm[2][0]);
+    if (!(std::fabs(J) >= 1e-12 * h * h * h) || !std::isfinite(J)) {
+      delete m;
+      return fail(DGM_ERR_MESH_DEGENERATE, "degenerate element " + std::to_string(e));
+    }
+    std::memcpy(&m->F[9 * e], Fm, sizeof(Fm));
+    m->J[e] = J;
+  }
+  // faces: local face f is opposite local vertex f; key = its sorted vertex triple
+  struct FaceRec {
+    int64_t a, b, c;
+    int64_t e;
+    int f;
+  };
+  std::vector<FaceRec> faces;
+  faces.reserve(4 * nt);
+  for (int64_t e = 0; e < nt; ++e)
+    for (int f = 0; f < 4; ++f) {
+      int64_t id[3];
+      int q = 0;
+      for (int v = 0; v < 4; ++v)
+        if (v != f) id[q++] = sorted[4 * e + v];
+      faces.push_back({id[0], id[1], id[2], e, f});
+    }
+  std::sort(faces.begin(), faces.end(), [](const FaceRec& x, const FaceRec& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.e < y.e;
+  });
+  m->nbr.assign(4 * nt, -1);
+  for (size_t s = 0; s < faces.size();) {
+    size_t t = s + 1;
+    while (t < faces.size() && faces[t].a == faces[s].a && faces[t].b == faces[s].b && faces[t].c == faces[s].c) ++t;
+    if (t - s > 2) {
+      delete m;
+      return fail(DGM_ERR_MESH_NONMANIFOLD, "face shared by more than two elements");
+    }
+    if (t - s == 2) {
+      const FaceRec &x = faces[s], &y = faces[s + 1];
+      if (x.e == y.e) {
+        delete m;
+        return fail(DGM_ERR_MESH_DEGENERATE, "element touches itself");
+      }
+      m->nbr[x.f * nt + x.e] = (int)(y.e * 4 + y.f);
+      m->nbr[y.f * nt + y.e] = (int)(x.e * 4 + x.f);
+    }
+    s = t;
+  }
+  int rc = upload(&m->d_nbr, m->nbr);
+  if (!rc) rc = material_impl(m, nullptr, nullptr);
+  if (rc) {
+    dgm_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return DGM_OK;
+}
+
+int dgm_destroy(dgm_mesh* m) {
+  if (!m) return DGM_OK;
+  hipFree(m->d_nbr);
+  for (int f = 0; f < 2; ++f) {
+    hipFree(m->d_M32[f]);
+    hipFree(m->d_M64[f]);
+    hipFree(m->d_Minv32[f]);
+    hipFree(m->d_Minv64[f]);
+    hipFree(m->d_G[f]);
+  }
+  hipFree(m->d_scratch);
+  hipFree(m->d_partial);
+  delete m;
+  return DGM_OK;
+}
+
+int dgm_num_elements(const dgm_mesh* m, int64_t* K) {
+  if (!m || !K) return fail(DGM_ERR_ARG, "null argument");
+  *K = m->K;
+  return DGM_OK;
+}
+
+int dgm_set_order(dgm_mesh* m, int p) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  if (p < 1 || p > DGM_MAX_ORDER_F32) return fail(DGM_ERR_ARG, "order out of range");
+  m->p = p;
+  return DGM_OK;
+}
+
+int dgm_set_material(dgm_mesh* m, const double* eps, const double* mu) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  return material_impl(m, eps, mu);
+}
+
+int dgm_apply_curl(dgm_mesh* m, int dtype, const void* E, const void* H, void* dE, void* dH, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if ((dH && !E) || (dE && !H)) return fail(DGM_ERR_ARG, "output requested without its input");
+  if ((dH && (dH == E || dH == H)) || (dE && (dE == E || dE == H))) return fail(DGM_ERR_ARG, "outputs alias inputs");
+  if (dtype == DGM_F32) {
+    if (dH && (rc = rate_impl<float>(m, (const float*)E, (float*)dH, 0, s))) return rc;
+    if (dE && (rc = rate_impl<float>(m, (const float*)H, (float*)dE, 1, s))) return rc;
+  } else {
+    if (dH && (rc = rate_impl<double>(m, (const double*)E, (double*)dH, 0, s))) return rc;
+    if (dE && (rc = rate_impl<double>(m, (const double*)H, (double*)dE, 1, s))) return rc;
+  }
+  return DGM_OK;
+}
+
+int dgm_step(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
+  return dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s)
+                          : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s);
+}
+
+int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void* Hn, double dt, double out[2],
+               hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if (!E || !H || !out) return fail(DGM_ERR_ARG, "null argument");
+  return dtype == DGM_F32 ? energy_impl<float>(m, (const float*)E, (const float*)H, (const float*)Hn, dt, out, s)
+                          : energy_impl<double>(m, (const double*)E, (const double*)H, (const double*)Hn, dt, out, s);
+}
+
+int dgm_estimate_dt(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
+  int rc = check_order(m, DGM_F64);
+  if (rc) return rc;
+  if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  double* x = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), 3 * n * sizeof(double) + 4 * sizeof(double), s));
+  double* const base = x;
+  double* y = x + n;
+  double* z = y + n;
+  double* d = z + n;
+  const int threads = 256;
+  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+  hipLaunchKernelGGL(splitmix_fill_kernel, dim3(blocks), dim3(threads), 0, s, x, n, (unsigned long long)seed);
+  HIP_TRY(hipGetLastError());
+  for (int it = 0; it < iters && !rc; ++it) {
+    // z = dH(dE(x)) = -B x, where B = M_mu^{-1} C M_eps^{-1} C^T is similar to the
+    // symmetric matrix of the bound; Rayleigh quotient in the M_mu inner product
+    if ((rc = rate_impl<double>(m, x, y, 1, s))) break;
+    if ((rc = rate_impl<double>(m, y, z, 0, s))) break;
+    if ((rc = mdot<double>(m, x, z, 1, d + 0, s))) break;
+    if ((rc = mdot<double>(m, x, x, 1, d + 1, s))) break;
+    if ((rc = mdot<double>(m, z, z, 1, d + 2, s))) break;
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(threads), 0, s, z, n, d + 2);
+    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
+    std::swap(x, z);
+  }
+  double h[3] = {0, 0, 0};
+  if (!rc) {
+    HIP_TRY(hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipFreeAsync(base, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rc) return rc;
+  const double rho = -h[0] / h[1];
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
+  if (rho_out) *rho_out = rho;
+  *dt = cfl * 2.0 / std::sqrt(rho);
+  return DGM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,16 @@
+// Launch arguments shared by the generated per-order phase kernels and the host code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+template <typename R>
+struct PhaseArgs {
+  const R* U;       // (3,N,K) stored-frame field that is differentiated
+  R* V;             // (3,N,K) stored-frame field updated in place: V += sdt * rate
+  const R* MU;      // (6,K) symmetric conversion of U into the derivative frame
+  const int* nbr;   // (4,K) neighbour code nb*4 + neighbour's local face, -1 on walls
+  R sdt;            // signed step: -dt (H update) or +dt (E update); -1/+1 for a bare rate
+  R wall;           // ghost factor on walls: -1 (E_nb = -E) or +1 (H_nb = H)
+  int K;            // number of elements
+  int blocks;       // ceil(K / 64)
+  hipStream_t stream;
+};

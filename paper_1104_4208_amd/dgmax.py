@@ -1,0 +1,226 @@
+"""Thin ctypes binding of libdgmax.so (include/dgmax.h).
+
+Argument marshalling only: every operation runs in the library's HIP kernels
+on the caller's current torch stream.  Field tensors are CUDA (HIP) tensors of
+shape (3, N, K), contiguous, float32 or float64, holding reference covariant
+modal coefficients in the library's mode order.  There is no fallback: if the
+shared library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgmax.so")
+
+DGM_F32, DGM_F64 = 0, 1
+ERRORS = {
+    -1: "DGM_ERR_ARG", -2: "DGM_ERR_MESH_DEGENERATE", -3: "DGM_ERR_MESH_NONMANIFOLD", -4: "DGM_ERR_MATERIAL",
+    -5: "DGM_ERR_OOM", -6: "DGM_ERR_HIP", -7: "DGM_ERR_UNSTABLE", -8: "DGM_ERR_STATE",
+}
+
+_c_i = ctypes.c_int
+_c_i64 = ctypes.c_int64
+_c_d = ctypes.c_double
+_c_p = ctypes.c_void_p
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi = ctypes.POINTER(ctypes.c_int)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+# name -> (restype, argtypes): every symbol declared in include/dgmax.h
+SIGNATURES = {
+    "dgm_last_error": (ctypes.c_char_p, []),
+    "dgm_num_modes": (_c_i, [_c_i]),
+    "dgm_num_face_modes": (_c_i, [_c_i]),
+    "dgm_max_order": (_c_i, [_c_i]),
+    "dgm_mode_index": (_c_i, [_c_i, _c_i, _pi, _pi, _pi]),
+    "dgm_create_mesh": (_c_i, [_pd, _c_i64, _pi64, _c_i64, ctypes.POINTER(_c_p)]),
+    "dgm_destroy": (_c_i, [_c_p]),
+    "dgm_num_elements": (_c_i, [_c_p, _pi64]),
+    "dgm_set_order": (_c_i, [_c_p, _c_i]),
+    "dgm_set_material": (_c_i, [_c_p, _pd, _pd]),
+    "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
+    "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
+    "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
+}
+
+_lib = None
+
+
+class DGMError(RuntimeError):
+    pass
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdgmax.so and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DGMError(f"{path} is missing: build it with `python -m paper_1104_4208_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = load_library().dgm_last_error().decode(errors="replace")
+        raise DGMError(f"{ERRORS.get(rc, rc)}: {msg}")
+
+
+def num_modes(p: int) -> int:
+    return load_library().dgm_num_modes(p)
+
+
+def num_face_modes(p: int) -> int:
+    return load_library().dgm_num_face_modes(p)
+
+
+def max_order(dtype: int = DGM_F32) -> int:
+    return load_library().dgm_max_order(dtype)
+
+
+def mode_index(p: int, m: int):
+    i, j, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().dgm_mode_index(p, m, ctypes.byref(i), ctypes.byref(j), ctypes.byref(k)))
+    return i.value, j.value, k.value
+
+
+def mode_table(p: int):
+    return [mode_index(p, m) for m in range(num_modes(p))]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return DGM_F32
+    if t.dtype == torch.float64:
+        return DGM_F64
+    raise DGMError("field tensors must be float32 or float64")
+
+
+class Mesh:
+    """A tetrahedral mesh on the device, with order and material."""
+
+    def __init__(self, verts, tets):
+        lib = load_library()
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
+        t = np.ascontiguousarray(np.asarray(tets, dtype=np.int64))
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 4:
+            raise DGMError("verts must be (nv,3) and tets (nt,4)")
+        h = ctypes.c_void_p()
+        _check(lib.dgm_create_mesh(v.ctypes.data_as(_pd), v.shape[0], t.ctypes.data_as(_pi64), t.shape[0],
+                                   ctypes.byref(h)))
+        self._h = h
+        self.K = int(t.shape[0])
+        self.p = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().dgm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def N(self):
+        return num_modes(self.p)
+
+    def set_order(self, p: int):
+        _check(load_library().dgm_set_order(self._h, int(p)))
+        self.p = int(p)
+        return self
+
+    def set_material(self, eps=None, mu=None):
+        def arr(x):
+            if x is None:
+                return None, None
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (self.K,)))
+            return a, a.ctypes.data_as(_pd)
+
+        ea, ep = arr(eps)
+        ma, mp = arr(mu)
+        _check(load_library().dgm_set_material(self._h, ep, mp))
+        return self
+
+    def _field(self, t, name):
+        torch = _torch()
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise DGMError(f"{name} must be a device tensor")
+        if tuple(t.shape) != (3, self.N, self.K) or not t.is_contiguous():
+            raise DGMError(f"{name} must be contiguous with shape (3, {self.N}, {self.K})")
+        return t
+
+    def zeros(self, dtype=None):
+        torch = _torch()
+        return torch.zeros((3, self.N, self.K), dtype=dtype or torch.float32, device="cuda")
+
+    def apply_curl(self, E=None, H=None, dE=None, dH=None):
+        """Returns (dE, dH) = (-M_eps^{-1} C^T H, M_mu^{-1} C E)."""
+        E, H = self._field(E, "E"), self._field(H, "H")
+        ref = E if E is not None else H
+        code = _dtype_code(ref)
+        torch = _torch()
+        if H is not None and dE is None:
+            dE = torch.empty_like(H)
+        if E is not None and dH is None:
+            dH = torch.empty_like(E)
+        _check(load_library().dgm_apply_curl(
+            self._h, code, _ptr(E), _ptr(H), _ptr(dE if H is not None else None),
+            _ptr(dH if E is not None else None), _stream()))
+        return (dE if H is not None else None), (dH if E is not None else None)
+
+    def step(self, E, H, dt: float, nsteps: int = 1):
+        E, H = self._field(E, "E"), self._field(H, "H")
+        if E.dtype != H.dtype:
+            raise DGMError("E and H must share a dtype")
+        _check(load_library().dgm_step(self._h, _dtype_code(E), _ptr(E), _ptr(H), float(dt), int(nsteps), _stream()))
+        return E, H
+
+    def energy(self, E, H, H_next=None, dt: float = 0.0):
+        """(W, Q) in FP64; Q uses H_next (computed as H + dt dH(E) when None)."""
+        E, H, Hn = self._field(E, "E"), self._field(H, "H"), self._field(H_next, "H_next")
+        out = (ctypes.c_double * 2)()
+        _check(load_library().dgm_energy(self._h, _dtype_code(E), _ptr(E), _ptr(H), _ptr(Hn), float(dt), out,
+                                         _stream()))
+        return out[0], out[1]
+
+    def estimate_dt(self, cfl: float = 0.5, iters: int = 50, seed: int = 1):
+        dt, rho = ctypes.c_double(), ctypes.c_double()
+        _check(load_library().dgm_estimate_dt(self._h, float(cfl), int(iters), int(seed), ctypes.byref(dt),
+                                              ctypes.byref(rho), _stream()))
+        return dt.value, rho.value
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())

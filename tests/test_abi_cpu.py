@@ -1,0 +1,68 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, reports the mode order, and rejects bad meshes before any
+device allocation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1104_4208_amd as P
+from paper_1104_4208_amd import dgmax as D
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dgmax.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = P.load_library()
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in D.SIGNATURES, f"binding misses {s}"
+    assert set(D.SIGNATURES) == set(syms)
+
+
+def test_mode_counts_and_order():
+    for p in range(0, 9):
+        assert P.num_modes(p) == (p + 1) * (p + 2) * (p + 3) // 6
+        assert P.num_face_modes(p) == (p + 1) * (p + 2) // 2
+    for p in (1, 4, 6):
+        tab = P.mode_table(p)
+        assert len(set(tab)) == len(tab)
+        deg = [sum(m) for m in tab]
+        assert deg == sorted(deg)
+        assert all(0 <= min(m) and sum(m) <= p for m in tab)
+    with pytest.raises(P.DGMError):
+        P.mode_index(2, 10)
+    assert P.max_order(P.DGM_F32) >= 8 and P.max_order(P.DGM_F64) >= 6
+
+
+def _create(verts, tets):
+    lib = P.load_library()
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tets, dtype=np.int64)
+    h = ctypes.c_void_p()
+    rc = lib.dgm_create_mesh(v.ctypes.data_as(D._pd), v.shape[0], t.ctypes.data_as(D._pi64), t.shape[0], ctypes.byref(h))
+    return rc, lib.dgm_last_error().decode()
+
+
+def test_mesh_errors_are_reported_before_device_work():
+    flat = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], float)
+    assert _create(flat, [[0, 1, 2, 3]])[0] == -2
+    assert _create(flat, [[0, 1, 2, 2]])[0] == -2
+    assert _create(flat, [[0, 1, 2, 7]])[0] == -1
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]], float)
+    rc, msg = _create(v, [[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]])
+    assert rc == -3 and "more than two" in msg
+    lib = P.load_library()
+    assert lib.dgm_create_mesh(None, 0, None, 0, None) == -1
+    assert lib.dgm_set_order(None, 2) == -1
+    assert lib.dgm_step(None, 0, None, None, 0.1, 1, None) == -1

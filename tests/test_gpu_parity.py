@@ -1,0 +1,213 @@
+"""HIP path against the FP64 oracle, element by element, through the C-ABI.
+
+Tolerances: FP64 mode 1e-10 relative (the oracle's own rounding is ~1e-13);
+FP32 mode 1e-5 relative to the largest coefficient for one operator
+application and over whole runs (rounding of a non-dissipative scheme grows
+at most linearly with the step count; measured margins are printed).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import Pair, patch, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1104_4208_amd as P  # noqa: E402
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+MESHES = {
+    "one": lambda rng: synth.single_tet(np.array([[0.1, 0, 0], [1, 0.2, 0], [0, 1.1, 0.1], [0.2, 0.1, 0.9]])),
+    "two_unsorted": lambda rng: synth.two_tets(rng),
+    "cube1": lambda rng: synth.kuhn_mesh(1),
+    "jit2": lambda rng: synth.kuhn_mesh(2, 0.1, rng),
+    "jit3_ragged": lambda rng: synth.kuhn_mesh(3, 0.1, rng),  # K = 162: two full tiles + 34
+}
+
+
+def _materials(rng, K):
+    return rng.uniform(1.0, 4.0, K), rng.uniform(1.0, 2.0, K)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("mesh", list(MESHES))
+def test_apply_curl_parity(mesh, p, dtype):
+    if dtype == "f64" and p > P.max_order(P.DGM_F64):
+        pytest.skip("order not compiled for FP64")
+    if p >= 6 and mesh in ("jit3_ragged",):
+        pytest.skip("covered at lower orders; keeps the oracle fast")
+    rng = np.random.default_rng(100 + p)
+    verts, tets = MESHES[mesh](rng)
+    K = tets.shape[0]
+    eps, mu = _materials(rng, K)
+    pr = Pair(verts, tets, p, eps, mu)
+    E = rng.standard_normal((K, pr.s.N, 3))
+    H = rng.standard_normal((K, pr.s.N, 3))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, mu)
+    dE, dH = m.apply_curl(dev(pr.to_cov(E), tdt), dev(pr.to_cov(H), tdt))
+    ref_dh = pr.to_cov(pr.s.rhs_h(E))
+    ref_de = pr.to_cov(pr.s.rhs_e(H))
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    eh, ee = rel_err(host(dH), ref_dh), rel_err(host(dE), ref_de)
+    print(f"{mesh} p={p} {dtype}: dH {eh:.2e} dE {ee:.2e}")
+    assert eh < tol and ee < tol
+
+
+def test_operator_brute_force_two_tets():
+    """Assemble the library's operator column by column and compare every entry."""
+    rng = np.random.default_rng(5)
+    verts, tets = synth.two_tets(rng)
+    p = 2
+    eps, mu = _materials(rng, 2)
+    pr = Pair(verts, tets, p, eps, mu)
+    Ah, Ae = pr.s.assemble()
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, mu)
+    n = 2 * pr.s.N * 3
+    for col in range(n):
+        u = np.zeros(n)
+        u[col] = 1.0
+        U = u.reshape(2, pr.s.N, 3)
+        Ucov = dev(pr.to_cov(U), torch.float64)
+        dE, dH = m.apply_curl(Ucov, Ucov)
+        assert rel_err(pr.to_phys(host(dH)).ravel(), Ah[:, col]) < 1e-10 or np.abs(Ah[:, col]).max() < 1e-14
+        assert rel_err(pr.to_phys(host(dE)).ravel(), Ae[:, col]) < 1e-10 or np.abs(Ae[:, col]).max() < 1e-14
+
+
+def _te101_setup(n, p, jitter=0.0, seed=1):
+    rng = np.random.default_rng(seed)
+    verts, tets = synth.kuhn_mesh(n, jitter, rng if jitter else None)
+    pr = Pair(verts, tets, p)
+    E = pr.s.project(synth.te101().E)
+    H = np.zeros_like(E)
+    rho = pr.s.spectral_radius(40, synth.splitmix64(seed, E.size))
+    dt = 1.0 / math.sqrt(rho)  # CFL 0.5 of the bound 2 / sqrt(rho)
+    return verts, tets, pr, E, H, dt
+
+
+def test_step_parity_cube2_p2_fp64():
+    """48 tets, p = 2, TE101, 100 steps: every 10th step within 1e-10; Q conserved."""
+    verts, tets, pr, E, H, dt = _te101_setup(2, 2)
+    m = P.Mesh(verts, tets).set_order(2)
+    Eg, Hg = dev(pr.to_cov(E), torch.float64), dev(pr.to_cov(H), torch.float64)
+    W0, Q0 = m.energy(Eg, Hg, dt=dt)
+    assert abs(W0 - pr.s.energy(E, H)) < 1e-12 * W0
+    assert abs(Q0 - pr.s.leapfrog_invariant(E, H, dt)) < 1e-12 * Q0
+    worst = 0.0
+    for blk in range(10):
+        m.step(Eg, Hg, dt, 10)
+        E, H = pr.s.step(E, H, dt, 10)
+        err = pr.s.rel_error(pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), E, H)
+        worst = max(worst, err)
+        assert err < 1e-10, (blk, err)
+    W, Q = m.energy(Eg, Hg, dt=dt)
+    print(f"cube2 p2 f64: worst rel err {worst:.2e}, Q drift {abs(Q - Q0) / Q0:.2e}")
+    assert abs(Q - Q0) < 1e-12 * Q0
+
+
+def test_step_parity_fp32_jittered_p4():
+    """FP32 run against the FP64 oracle: 200 steps on a jittered 3^3 mesh with eps in {1,4}."""
+    rng = np.random.default_rng(2)
+    verts, tets = synth.kuhn_mesh(3, 0.1, rng)
+    K = tets.shape[0]
+    eps = rng.choice([1.0, 4.0], size=K)
+    pr = Pair(verts, tets, 4, eps, None)
+    fld = synth.three_mode_sum(rng)
+    E = pr.s.project(fld.E)
+    H = np.zeros_like(E)
+    rho = pr.s.spectral_radius(40, synth.splitmix64(2, E.size))
+    dt = 1.0 / math.sqrt(rho)
+    m = P.Mesh(verts, tets).set_order(4).set_material(eps, None)
+    Eg, Hg = dev(pr.to_cov(E), torch.float32), dev(pr.to_cov(H), torch.float32)
+    _, Q0 = m.energy(Eg, Hg, dt=dt)
+    worst = 0.0
+    for blk in range(4):
+        m.step(Eg, Hg, dt, 50)
+        E, H = pr.s.step(E, H, dt, 50)
+        err = pr.s.rel_error(pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), E, H)
+        worst = max(worst, err)
+    _, Q = m.energy(Eg, Hg, dt=dt)
+    print(f"jit3 p4 f32 200 steps: worst rel err {worst:.2e}, Q drift {abs(Q - Q0) / Q0:.2e}")
+    assert worst < 1e-5
+    assert abs(Q - Q0) < 1e-6 * Q0
+
+
+def test_estimate_dt_matches_spectrum():
+    verts, tets = synth.kuhn_mesh(1)
+    pr = Pair(verts, tets, 2)
+    Ah, Ae = pr.s.assemble()
+    rho = float(np.max(np.linalg.eigvals(-Ah @ Ae).real))
+    m = P.Mesh(verts, tets).set_order(2)
+    dt, est = m.estimate_dt(cfl=0.5, iters=300, seed=3)
+    assert 0.999 * rho < est <= rho * (1 + 1e-9)
+    assert abs(dt - 0.5 * 2 / math.sqrt(est)) < 1e-15
+
+
+def test_deterministic_and_ragged():
+    rng = np.random.default_rng(9)
+    verts, tets = synth.kuhn_mesh(3, 0.1, rng)
+    m = P.Mesh(verts, tets).set_order(3)
+    K, N = tets.shape[0], P.num_modes(3)
+    E0 = dev(rng.standard_normal((3, N, K)), torch.float32)
+    H0 = dev(rng.standard_normal((3, N, K)), torch.float32)
+    outs = []
+    for _ in range(2):
+        E, H = E0.clone(), H0.clone()
+        m.step(E, H, 1e-3, 7)
+        outs.append((host(E), host(H)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_zero_steps_and_errors():
+    verts, tets = synth.kuhn_mesh(1)
+    m = P.Mesh(verts, tets)
+    E = torch.zeros((3, 10, 6), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.DGMError):
+        P.load_library()
+        from paper_1104_4208_amd.dgmax import _check, _ptr, _stream
+        _check(P.load_library().dgm_step(m.handle, 0, _ptr(E), _ptr(E.clone()), 0.1, 1, _stream()))
+    m.set_order(2)
+    H = E.clone()
+    m.step(E, H, 0.1, 0)
+    with pytest.raises(P.DGMError):
+        m.set_material(np.full(6, -1.0), None)
+
+
+@pytest.mark.parametrize("n,p", [(32, 6), (16, 4), (24, 8)])
+def test_full_size_sampled_apply_curl(n, p):
+    """At the benchmark sizes and launch configuration: apply_curl on the whole mesh,
+    checked on sampled elements against the oracle on patch meshes."""
+    rng = np.random.default_rng(n)
+    verts, tets = synth.kuhn_mesh(n, 0.1, rng)
+    K = tets.shape[0]
+    eps = rng.choice([1.0, 4.0], size=K)
+    N = P.num_modes(p)
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
+    Ecov = rng.standard_normal((3, N, K)).astype(np.float32)
+    Hcov = rng.standard_normal((3, N, K)).astype(np.float32)
+    dE, dH = m.apply_curl(dev(Ecov, torch.float32), dev(Hcov, torch.float32))
+    dE, dH = host(dE), host(dH)
+    centers = np.unique(np.concatenate([rng.integers(0, K, 12), [0, K - 1]]))
+    keep, ptets, pos = patch(tets, centers)
+    pr = Pair(verts, ptets, p, eps[keep], None)
+    Ep = pr.to_phys(Ecov[:, :, keep].astype(np.float64))
+    Hp = pr.to_phys(Hcov[:, :, keep].astype(np.float64))
+    ref_dh = pr.to_cov(pr.s.rhs_h(Ep))[:, :, pos]
+    ref_de = pr.to_cov(pr.s.rhs_e(Hp))[:, :, pos]
+    eh = rel_err(dH[:, :, centers], ref_dh)
+    ee = rel_err(dE[:, :, centers], ref_de)
+    print(f"n={n} p={p} sampled {len(centers)}: dH {eh:.2e} dE {ee:.2e}")
+    assert eh < 1e-5 and ee < 1e-5
