@@ -91,70 +91,290 @@ def _assign(jobs, costs, nw):
     return out, load
 
 
+TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
+
+
+PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
+
+
+class _Stream:
+    """Emit a stream of mode blocks as separate basic blocks with explicit prefetch.
+
+    Every block sits behind an opaque uniform branch (an offset that is zero but
+    hidden from the compiler by an empty asm statement), so instruction
+    scheduling stays inside one block and register pressure stays bounded; the
+    loads of block b + PREFETCH are issued inside block b into a small ring of
+    registers, which keeps memory latency hidden without hoisting every load of
+    the stream to its start.
+    """
+
+    def __init__(self, a_, ind, tag):
+        self.a_, self.ind, self.tag = a_, ind, tag
+
+    def emit(self, blocks):
+        """blocks: list of (loads, body) with loads = [load expressions, may use o] and
+        body(names) -> list of statements using the loaded values."""
+        a_, ind, tag = self.a_, self.ind, self.tag
+        if not blocks:
+            return
+        nl = max(len(ld) for ld, _ in blocks)
+        slots = [[f"{tag}{r}_{q}" for q in range(nl)] for r in range(PREFETCH)]
+        a_(ind + "R " + ", ".join(f"{v} = R(0)" for r in slots for v in r) + ";")
+        a_(ind + "size_t o = 0;")
+        for bi in range(min(PREFETCH, len(blocks))):
+            for q, expr in enumerate(blocks[bi][0]):
+                a_(ind + f"{slots[bi][q]} = {expr};")
+        for bi, (ld, body) in enumerate(blocks):
+            r = bi % PREFETCH
+            a_(ind + "asm volatile(\"\" : \"+s\"(o));")
+            a_(ind + "if (o == 0) {")
+            names = [f"x{q}" for q in range(len(ld))]
+            for q in range(len(ld)):
+                a_(ind + f"  const R {names[q]} = {slots[r][q]};")
+            nxt = bi + PREFETCH
+            if nxt < len(blocks):
+                for q, expr in enumerate(blocks[nxt][0]):
+                    a_(ind + f"  {slots[r][q]} = {expr};")
+            for st in body(names):
+                a_(ind + "  " + st)
+            a_(ind + "}")
+
+
+def _chunks(items, costs, max_cost):
+    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
+    out, cur, c = [], [], 0
+    for it, w in zip(items, costs):
+        if cur and c + w > max_cost:
+            out.append(cur)
+            cur, c = [], 0
+        cur.append(it)
+        c += w
+    if cur:
+        out.append(cur)
+    return out
+
+
+def _assign(jobs, costs, nw):
+    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
+    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
+    load = [0] * nw
+    out = [[] for _ in range(nw)]
+    for i in order:
+        w = min(range(nw), key=lambda k: load[k])
+        out[w].append(jobs[i])
+        load[w] += costs[i]
+    return out, load
+
+
+TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
+
+
+def _chunks(items, costs, max_cost):
+    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
+    out, cur, c = [], [], 0
+    for it, w in zip(items, costs):
+        if cur and c + w > max_cost:
+            out.append(cur)
+            cur, c = [], 0
+        cur.append(it)
+        c += w
+    if cur:
+        out.append(cur)
+    return out
+
+
+def _assign(jobs, costs, nw):
+    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
+    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
+    load = [0] * nw
+    out = [[] for _ in range(nw)]
+    for i in order:
+        w = min(range(nw), key=lambda k: load[k])
+        out[w].append(jobs[i])
+        load[w] += costs[i]
+    return out, load
+
+
+TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
+
+
+PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
+
+
+class _Stream:
+    """Emit a stream of mode blocks as separate basic blocks with explicit prefetch.
+
+    Every block sits behind an opaque uniform branch (an offset that is zero but
+    hidden from the compiler by an empty asm statement), so instruction
+    scheduling stays inside one block and register pressure stays bounded; the
+    loads of block b + PREFETCH are issued inside block b into a small ring of
+    registers, which keeps memory latency hidden without hoisting every load of
+    the stream to its start.
+    """
+
+    def __init__(self, a_, ind, tag):
+        self.a_, self.ind, self.tag = a_, ind, tag
+
+    def emit(self, blocks):
+        """blocks: list of (loads, body) with loads = [load expressions, may use o] and
+        body(names) -> list of statements using the loaded values."""
+        a_, ind, tag = self.a_, self.ind, self.tag
+        if not blocks:
+            return
+        nl = max(len(ld) for ld, _ in blocks)
+        slots = [[f"{tag}{r}_{q}" for q in range(nl)] for r in range(PREFETCH)]
+        a_(ind + "R " + ", ".join(f"{v} = R(0)" for r in slots for v in r) + ";")
+        a_(ind + "size_t o = 0;")
+        for bi in range(min(PREFETCH, len(blocks))):
+            for q, expr in enumerate(blocks[bi][0]):
+                a_(ind + f"{slots[bi][q]} = {expr};")
+        for bi, (ld, body) in enumerate(blocks):
+            r = bi % PREFETCH
+            a_(ind + "asm volatile(\"\" : \"+s\"(o));")
+            a_(ind + "if (o == 0) {")
+            names = [f"x{q}" for q in range(len(ld))]
+            for q in range(len(ld)):
+                a_(ind + f"  const R {names[q]} = {slots[r][q]};")
+            nxt = bi + PREFETCH
+            if nxt < len(blocks):
+                for q, expr in enumerate(blocks[nxt][0]):
+                    a_(ind + f"  {slots[r][q]} = {expr};")
+            for st in body(names):
+                a_(ind + "  " + st)
+            a_(ind + "}")
+
+
+def _chunks(items, costs, max_cost):
+    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
+    out, cur, c = [], [], 0
+    for it, w in zip(items, costs):
+        if cur and c + w > max_cost:
+            out.append(cur)
+            cur, c = [], 0
+        cur.append(it)
+        c += w
+    if cur:
+        out.append(cur)
+    return out
+
+
+def _assign(jobs, costs, nw):
+    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
+    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
+    load = [0] * nw
+    out = [[] for _ in range(nw)]
+    for i in order:
+        w = min(range(nw), key=lambda k: load[k])
+        out[w].append(jobs[i])
+        load[w] += costs[i]
+    return out, load
+
+
+TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
+
+
+class _Window:
+    """Software-pipelining window for a stream of mode blocks.
+
+    The compiler would otherwise hoist every load of a straight-line stream to
+    its start (one basic block), holding hundreds of values in registers.  Each
+    block's address offset passes through an empty asm statement that consumes
+    a token produced by the block WINDOW places earlier, so at most WINDOW
+    blocks of loads are in flight and the offset keeps its global address space.
+    """
+
+    def __init__(self, a_, ind, tag):
+        self.a_, self.ind, self.tag, self.n = a_, ind, tag, 0
+        a_(ind + "R " + ", ".join(f"{tag}{i} = R(0)" for i in range(WINDOW)) + ";")
+
+    def begin(self):
+        i = self.n % WINDOW
+        self.a_(self.ind + f"size_t o = 0; asm volatile(\"\" : \"+s\"(o) : \"v\"({self.tag}{i}));")
+        return i
+
+    def end(self, i, value):
+        self.a_(self.ind + f"{self.tag}{i} = {value};")
+        self.n += 1
+
+OUT_ROWS = 16     # volume modes per output job (3 components each)
+CYC = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
+
+
+def _lift_per_scalar(t, f, rows, Lp):
+    """Lift the two jumps separately (2 nnz + combine) when cheaper than one lift per
+    component that face f reaches (one nnz each)."""
+    nnz = int(np.count_nonzero(t.T[f][:, rows]))
+    ncomp = sum(1 for k in range(3) if np.any(Lp[f][k] != 0))
+    return 2 * nnz + 2 * ncomp * len(rows) < ncomp * nnz
+
+
 def plan(p: int, nw: int = WAVES):
-    """Split the work of one phase into trace jobs (face f, face rows) and output jobs
-    (component k, volume rows), balanced over nw waves by FMA count."""
+    """Split one phase into trace jobs (face f, face rows: own + neighbour traces) and
+    output jobs (volume rows, all three components), balanced over nw waves."""
     t = TB.build(p)
     N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
-    # trace jobs: cost = own trace + worst neighbour trace of those rows (2 scalars each)
     tr_items, tr_cost = [], []
     for f in range(4):
-        rows = list(range(NF))
-        rc = [2 * (np.count_nonzero(t.T[f][m]) + max(np.count_nonzero(t.T[h][m]) for h in range(4))) for m in rows]
-        tot = sum(2 * (np.count_nonzero(t.T[ff]) * 2) for ff in range(4))
-        for ch in _chunks(rows, rc, max(1, tot // (2 * nw))):
-            tr_items.append((f, ch))
-            tr_cost.append(sum(rc[m] for m in ch))
-    cyc = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
+        for r0 in range(0, NF, TRACE_ROWS):
+            rows = list(range(r0, min(NF, r0 + TRACE_ROWS)))
+            own = 2 * np.count_nonzero(t.T[f][rows]) + 6 * np.count_nonzero(np.any(t.T[f][rows] != 0, axis=0))
+            nb = max(2 * np.count_nonzero(t.T[h][rows]) + 6 * np.count_nonzero(np.any(t.T[h][rows] != 0, axis=0))
+                     for h in range(4))
+            tr_items.append((f, rows))
+            tr_cost.append(int(own + nb))
+    rc = []
+    for b in range(N):
+        c = sum(np.count_nonzero(t.D[d][b]) for d in range(3)) * 2 // 3 * 3 // 2
+        for f in range(4):
+            c += 2 * np.count_nonzero(t.T[f][:, b])
+        rc.append(c + 10)
     out_items, out_cost = [], []
-    for k in range(3):
-        i, j = cyc[k]
-        rows = list(range(N))
-        rc = []
-        for b in rows:
-            c = np.count_nonzero(t.D[i][b]) + np.count_nonzero(t.D[j][b])
-            for f in range(4):
-                if np.any(Lp[f][k] != 0):
-                    c += np.count_nonzero(t.T[f][:, b])
-            rc.append(c + 1)
-        tot = sum(rc)
-        for ch in _chunks(rows, rc, max(1, -(-tot // nw))):
-            out_items.append((k, ch))
-            out_cost.append(sum(rc[b] for b in ch))
+    tot = sum(rc) + 9 * N * nw
+    for ch in _chunks(list(range(N)), rc, max(1, tot // (2 * nw))):
+        for r0 in range(0, len(ch), OUT_ROWS):
+            rows = ch[r0:r0 + OUT_ROWS]
+            out_items.append(rows)
+            out_cost.append(sum(rc[b] for b in rows) + 9 * N)
     tr_w, tr_load = _assign(tr_items, tr_cost, nw)
     out_w, out_load = _assign(out_items, out_cost, nw)
     return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load)
 
 
-def _self_trace(a_, t, g, f, rows, ind):
-    """Own tangential traces of face f, face rows `rows`, into ts{k}_{m}."""
-    N = t.N
-    a_(ind + "R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
-    a_(ind + "{ const R* Ul = U; asm volatile(\"\" : \"+s\"(Ul));")
+def _hvec(a_, ind, g, f, M, name):
+    """h = M g for the two tangential directions of face f: tau = h . S."""
+    m = {(0, 0): M + "00", (0, 1): M + "01", (0, 2): M + "02", (1, 1): M + "11", (1, 2): M + "12", (2, 2): M + "22"}
+    sym = lambda r, c: m[(min(r, c), max(r, c))]
+    for k in range(2):
+        for r in range(3):
+            terms = [f"{_lit(g[f][k][c])} * {sym(r, c)}" for c in range(3) if g[f][k][c] != 0.0]
+            a_(ind + f"const R {name}{k}{r} = {' + '.join(terms) if terms else 'R(0)'};")
+
+
+def _trace_job(a_, t, g, f, rows, ind):
+    """Own and neighbour tangential traces of face f on face rows `rows`; the jump
+    (neighbour minus own) goes to LDS."""
+    N, NF = t.N, t.NF
+    a_(ind + "{")
+    a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
+    _hvec(a_, ind + "  ", g, f, "m", "h")
+    blocks = []
     for a in range(N):
         ms = [m for m in rows if t.T[f][m, a] != 0]
         if not ms:
             continue
-        a_(ind + "  {")
-        a_(ind + f"    const R s0 = Ul[({a}) * Ks + el], s1 = Ul[({N + a}) * Ks + el], s2 = Ul[({2 * N + a}) * Ks + el];")
-        a_(ind + "    const R w0 = m00 * s0 + m01 * s1 + m02 * s2;")
-        a_(ind + "    const R w1 = m01 * s0 + m11 * s1 + m12 * s2;")
-        a_(ind + "    const R w2 = m02 * s0 + m12 * s1 + m22 * s2;")
-        for k in range(2):
-            a_(ind + "    " + _dot(g[f][k], ["w0", "w1", "w2"], f"q{k}"))
-        for m in ms:
-            for k in range(2):
-                a_(ind + "    " + _fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
-        a_(ind + "  }")
-    a_(ind + "}")
 
+        def body(x, a=a, ms=ms):
+            out = [f"const R q0 = h00 * {x[0]} + h01 * {x[1]} + h02 * {x[2]}, q1 = h10 * {x[0]} + h11 * {x[1]} + h12 * {x[2]};"]
+            for m in ms:
+                for k in range(2):
+                    out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
+            return out
 
-def _nb_trace(a_, t, g, f, rows, ind):
-    """Neighbour tangential traces on face f (neighbour's own face code & 3) minus own,
-    stored to the jump buffer in LDS."""
-    N, NF = t.N, t.NF
-    a_(ind + "{")
+        blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
+    a_(ind + "  {")
+    _Stream(a_, ind + "    ", "pf").emit(blocks)
+    a_(ind + "  }")
     a_(ind + f"  const int code = nbr[{f} * Ks + el];")
     a_(ind + "  if (code < 0) {")
     for m in rows:
@@ -168,21 +388,22 @@ def _nb_trace(a_, t, g, f, rows, ind):
     a_(ind + "    switch (code & 3) {")
     for gf in range(4):
         a_(ind + f"    case {gf}: {{")
+        _hvec(a_, ind + "      ", g, gf, "n", "z")
+        blocks = []
         for a in range(N):
             ms = [m for m in rows if t.T[gf][m, a] != 0]
             if not ms:
                 continue
-            a_(ind + "      {")
-            a_(ind + f"        const R s0 = U[({a}) * Ks + nb], s1 = U[({N + a}) * Ks + nb], s2 = U[({2 * N + a}) * Ks + nb];")
-            a_(ind + "        const R w0 = n00 * s0 + n01 * s1 + n02 * s2;")
-            a_(ind + "        const R w1 = n01 * s0 + n11 * s1 + n12 * s2;")
-            a_(ind + "        const R w2 = n02 * s0 + n12 * s1 + n22 * s2;")
-            for k in range(2):
-                a_(ind + "        " + _dot(g[gf][k], ["w0", "w1", "w2"], f"q{k}"))
-            for m in ms:
-                for k in range(2):
-                    a_(ind + "        " + _fma(f"tn{k}_{m}", t.T[gf][m, a], f"q{k}"))
-            a_(ind + "      }")
+
+            def body(x, a=a, ms=ms, gf=gf):
+                out = [f"const R q0 = z00 * {x[0]} + z01 * {x[1]} + z02 * {x[2]}, q1 = z10 * {x[0]} + z11 * {x[1]} + z12 * {x[2]};"]
+                for m in ms:
+                    for k in range(2):
+                        out.append(_fma(f"tn{k}_{m}", t.T[gf][m, a], f"q{k}"))
+                return out
+
+            blocks.append(([f"U[o + ({a}) * Ks + nb]", f"U[o + ({N + a}) * Ks + nb]", f"U[o + ({2 * N + a}) * Ks + nb]"], body))
+        _Stream(a_, ind + "      ", "pn").emit(blocks)
         a_(ind + "      break;")
         a_(ind + "    }")
     a_(ind + "    }")
@@ -196,55 +417,95 @@ def _nb_trace(a_, t, g, f, rows, ind):
     a_(ind + "}")
 
 
-def _output(a_, t, Lp, k, rows, ind):
-    """Component k of the update for volume rows `rows`: curl in the derivative frame
-    plus the lifted face jumps read back from LDS."""
+def _output_job(a_, t, Lp, rows, ind):
+    """All three components of the update on volume rows `rows`: curl in the
+    derivative frame (one conversion per streamed mode) plus the lifted jumps."""
     N, NF = t.N, t.NF
-    cyc = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
-    i, j = cyc[k]
-    Mi = {0: "m00 * s0 + m01 * s1 + m02 * s2", 1: "m01 * s0 + m11 * s1 + m12 * s2", 2: "m02 * s0 + m12 * s1 + m22 * s2"}
-    rs = set(rows)
     a_(ind + "{")
-    a_(ind + "  R " + ", ".join(f"acc{b} = R(0)" for b in rows) + ";")
-    a_(ind + "  { const R* Ul = U; asm volatile(\"\" : \"+s\"(Ul));")
+    a_(ind + "  R " + ", ".join(f"acc{k}_{b} = R(0)" for b in rows for k in range(3)) + ";")
+    rowsM = {0: "m00 * {0} + m01 * {1} + m02 * {2}", 1: "m01 * {0} + m11 * {1} + m12 * {2}", 2: "m02 * {0} + m12 * {1} + m22 * {2}"}
+    blocks = []
     for a in range(N):
-        ri = [b for b in rows if t.D[i][b, a] != 0]
-        rj = [b for b in rows if t.D[j][b, a] != 0]
-        if not ri and not rj:
+        hits = {d: [b for b in rows if t.D[d][b, a] != 0] for d in range(3)}
+        if not any(hits.values()):
             continue
-        a_(ind + "    {")
-        a_(ind + f"      const R s0 = Ul[({a}) * Ks + el], s1 = Ul[({N + a}) * Ks + el], s2 = Ul[({2 * N + a}) * Ks + el];")
-        if ri:
-            a_(ind + f"      const R wj = {Mi[j]};")
-        if rj:
-            a_(ind + f"      const R wi = {Mi[i]};")
-        for b in ri:
-            a_(ind + "      " + _fma(f"acc{b}", t.D[i][b, a], "wj"))
-        for b in rj:
-            a_(ind + "      " + _fma(f"acc{b}", -t.D[j][b, a], "wi"))
-        a_(ind + "    }")
+        need = set()
+        for k in range(3):
+            i, j = CYC[k]
+            if hits[i]:
+                need.add(j)
+            if hits[j]:
+                need.add(i)
+
+        def body(x, a=a, hits=hits, need=need):
+            out = [f"const R w{c} = {rowsM[c].format(*x)};" for c in sorted(need)]
+            for k in range(3):
+                i, j = CYC[k]
+                for b in hits[i]:
+                    out.append(_fma(f"acc{k}_{b}", t.D[i][b, a], f"w{j}"))
+                for b in hits[j]:
+                    out.append(_fma(f"acc{k}_{b}", -t.D[j][b, a], f"w{i}"))
+            return out
+
+        blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
+    a_(ind + "  {")
+    _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
+    jd = lambda f, k, m: f"jmp[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
+    lblocks = []
+    scalar_faces = []
     for f in range(4):
-        c0, c1 = Lp[f][k]
-        if c0 == 0.0 and c1 == 0.0:
+        ks = [k for k in range(3) if np.any(Lp[f][k] != 0)]
+        ms = [m for m in range(NF) if np.any(t.T[f][m, rows] != 0)]
+        if not ks or not ms:
             continue
-        for m in range(NF):
-            bs = [b for b in rows if t.T[f][m, b] != 0]
-            if not bs:
+        per_scalar = _lift_per_scalar(t, f, rows, Lp)
+        if per_scalar:
+            scalar_faces.append((f, ks))
+        for m in ms:
+            def body(x, f=f, m=m, ks=ks, per_scalar=per_scalar):
+                out = []
+                for b in rows:
+                    c = t.T[f][m, b]
+                    if c == 0:
+                        continue
+                    if per_scalar:
+                        out.append(_fma(f"l{f}0_{b}", c, x[0]))
+                        out.append(_fma(f"l{f}1_{b}", c, x[1]))
+                for k in ks if not per_scalar else []:
+                    c0, c1 = Lp[f][k]
+                    terms = []
+                    if c0 != 0.0:
+                        terms.append(f"{_lit(c0)} * {x[0]}")
+                    if c1 != 0.0:
+                        terms.append(f"{_lit(c1)} * {x[1]}")
+                    out.append(f"const R g{k} = {' + '.join(terms)};")
+                    for b in rows:
+                        c = t.T[f][m, b]
+                        if c != 0:
+                            out.append(_fma(f"acc{k}_{b}", c, f"g{k}"))
+                return out
+            lblocks.append(([jd(f, 0, m), jd(f, 1, m)], body))
+    for f, ks in scalar_faces:
+        used = [b for b in rows if np.any(t.T[f][:, b] != 0)]
+        a_(ind + "  R " + ", ".join(f"l{f}{k}_{b} = R(0)" for b in used for k in range(2)) + ";")
+    a_(ind + "  {")
+    _Stream(a_, ind + "    ", "pj").emit(lblocks)
+    a_(ind + "  }")
+    for f, ks in scalar_faces:
+        for b in rows:
+            if not np.any(t.T[f][:, b] != 0):
                 continue
-            terms = []
-            if c0 != 0.0:
-                terms.append(f"{_lit(c0)} * jmp[({(f * 2 + 0) * NF + m}) * {LANES} + lane]")
-            if c1 != 0.0:
-                terms.append(f"{_lit(c1)} * jmp[({(f * 2 + 1) * NF + m}) * {LANES} + lane]")
-            a_(ind + "  {")
-            a_(ind + f"    const R gf = {' + '.join(terms)};")
-            for b in bs:
-                a_(ind + "    " + _fma(f"acc{b}", t.T[f][m, b], "gf"))
-            a_(ind + "  }")
+            for k in ks:
+                c0, c1 = Lp[f][k]
+                if c0 != 0.0:
+                    a_(ind + "  " + _fma(f"acc{k}_{b}", c0, f"l{f}0_{b}"))
+                if c1 != 0.0:
+                    a_(ind + "  " + _fma(f"acc{k}_{b}", c1, f"l{f}1_{b}"))
     a_(ind + "  if (act) {")
     for b in rows:
-        a_(ind + f"    V[({k * N + b}) * Ks + e] += sdt * acc{b};")
+        for k in range(3):
+            a_(ind + f"    V[({k * N + b}) * Ks + e] += sdt * acc{k}_{b};")
     a_(ind + "  }")
     a_(ind + "}")
 
@@ -257,9 +518,8 @@ def emit_phase(p: int, nw: int = WAVES) -> str:
     L = []
     a_ = L.append
     a_(f"// Generated by gen/emit.py for order p = {p}: N = {N} volume modes, NF = {NF} face modes.")
-    a_(f"// {nw} waves share {LANES} elements (one per lane); trace FMA load per wave {pl['trace_load']},")
-    a_(f"// output FMA load per wave {pl['out_load']}.")
-    a_(f"static constexpr int kJumpSlots_p{p} = {8 * NF};")
+    a_(f"// {nw} waves share {LANES} elements (one per lane); trace cost per wave {pl['trace_load']},")
+    a_(f"// output cost per wave {pl['out_load']}.")
     a_("template <typename R>")
     a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const int* __restrict__ nbr, R sdt, R wall, int K)")
@@ -283,18 +543,15 @@ def emit_phase(p: int, nw: int = WAVES) -> str:
         a_(f"  if (wave == {w}) {{")
         for (f, rows) in pl["trace"][w]:
             a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            a_("    {")
-            _self_trace(a_, t, g, f, rows, "      ")
-            _nb_trace(a_, t, g, f, rows, "      ")
-            a_("    }")
+            _trace_job(a_, t, g, f, rows, "    ")
         a_("  }")
     a_("  __syncthreads();")
     a_("  // stage 2: curl and lifted jumps, component-separable update")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
-        for (k, rows) in pl["out"][w]:
-            a_(f"    // component {k}, volume modes {rows[0]}..{rows[-1]}")
-            _output(a_, t, Lp, k, rows, "    ")
+        for rows in pl["out"][w]:
+            a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
+            _output_job(a_, t, Lp, rows, "    ")
         a_("  }")
     a_("}")
     return "\n".join(L) + "\n"
