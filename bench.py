@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-dense", action="store_true", help="skip the p=8 dense matrix-core comparison")
+    ap.add_argument("--dense-steps", type=int, default=200)
     return ap.parse_args()
 
 
@@ -90,6 +92,79 @@ def cpu_baseline(target_seconds: float):
     rate = 6 * s.N * K * n / el
     return {"value": rate, "unit": "DOF-updates/s", "cores": int(cores), "kind": "oracle",
             "sample": f"FP64 oracle, 4^3 x 6 = {K} jittered tets, p=6, eps in {{1,4}}, {n} steps in {el:.1f} s"}
+
+
+def dense_comparison(steps: int):
+    """p = 8 workload (24^3 x 6 = 82,944 tets, random modal data, seed 4): the FP32
+    sparse path against the dense matrix-core variant with BF16 and FP16 operands.
+    Reports time per step, DOF-updates/s, the error of one operator application
+    against the FP64 oracle on sampled elements, and the energy-norm distance of
+    each dense run from the FP32 run after `steps` steps."""
+    import torch
+
+    import oracle
+    import paper_1104_4208_amd as P
+    import synth
+    from paper_1104_4208_amd.gen.basis import volume_modes
+
+    w = synth.WORKLOADS["cube24_p8_dense"]
+    d = synth.build_workload(w)
+    rng = d["field"]
+    verts, tets = d["verts"], d["tets"]
+    K, p = tets.shape[0], w.p
+    N = P.num_modes(p)
+    m = P.Mesh(verts, tets).set_order(p)
+    # random physical Cartesian modal coefficients, mapped to the covariant layout
+    ts = np.sort(tets, axis=1)
+    Pv = verts[ts]
+    F = np.stack([Pv[:, 1] - Pv[:, 0], Pv[:, 2] - Pv[:, 0], Pv[:, 3] - Pv[:, 0]], axis=2)
+    e_phys = rng.standard_normal((K, N, 3))
+    E0 = np.ascontiguousarray(np.einsum("kji,kmj->imk", F, e_phys))
+    E = torch.tensor(E0, dtype=torch.float32, device="cuda")
+    H = torch.zeros_like(E)
+    W0, _ = m.energy(E, H)
+    E /= math.sqrt(W0)  # rescaled to W = 1
+    dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
+    out = {"workload": "pec_cube_kuhn24_p8_random_modes", "tets": K, "p": p, "dofs": 6 * N * K, "steps": steps, "dt": dt}
+    # sampled operator error against the oracle
+    centers = np.arange(0, K, K // 8)
+    import sys as _s
+    _s.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_helpers import Pair, patch, rel_err
+
+    keep, ptets, pos = patch(tets, centers)
+    pr = Pair(verts, ptets, p)
+    Hrand = torch.tensor(np.ascontiguousarray(rng.standard_normal((3, N, K))), dtype=torch.float32, device="cuda")
+    ref_de = pr.to_cov(pr.s.rhs_e(pr.to_phys(Hrand[:, :, keep].double().cpu().numpy())))[:, :, pos]
+    runs = {}
+    for name, prec in (("fp32_sparse", None), ("bf16_dense", P.DGM_BF16), ("fp16_dense", P.DGM_F16)):
+        if prec is None:
+            dE, _ = m.apply_curl(None, Hrand)
+        else:
+            dE, _ = m.apply_curl_dense(None, Hrand, prec=prec)
+        torch.cuda.synchronize()
+        err1 = rel_err(dE[:, :, centers].double().cpu().numpy(), ref_de)
+        Ei, Hi = E.clone(), H.clone()
+        stepf = (lambda a, b, n: m.step(a, b, dt, n)) if prec is None else (lambda a, b, n, q=prec: m.step_dense(a, b, dt, n, prec=q))
+        stepf(Ei, Hi, 2)
+        torch.cuda.synchronize()
+        Ei, Hi = E.clone(), H.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        stepf(Ei, Hi, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        runs[name] = (Ei, Hi)
+        out[name] = {"ms_per_step": sec / steps * 1e3, "dof_updates_per_s": 6 * N * K * steps / sec,
+                     "apply_rel_err_vs_oracle": err1}
+    Es, Hs = runs["fp32_sparse"]
+    Ws, _ = m.energy(Es, Hs)
+    for name in ("bf16_dense", "fp16_dense"):
+        Ed, Hd = runs[name]
+        Wd, _ = m.energy(Ed - Es, Hd - Hs)
+        out[name]["energy_norm_dist_from_fp32_after_run"] = math.sqrt(Wd / Ws)
+    return out
 
 
 def main():
@@ -159,6 +234,10 @@ def main():
                      "kernel": "dgm_phase_p6<float>", "phase_us": phase_s * 1e6, "bytes_per_launch": bytes_launch},
         "energy": {"W0": W0, "Q0": Q0, "Q_end": Q1, "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps_done},
     }
+    del E, H
+    torch.cuda.empty_cache()
+    if not a.no_dense:
+        out["dense_variant"] = dense_comparison(a.dense_steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -44,6 +44,8 @@ extern "C" {
 typedef struct dgm_mesh dgm_mesh;
 
 enum { DGM_F32 = 0, DGM_F64 = 1 };
+/* 16-bit operand precisions of the dense matrix-core variant (FP32 accumulation). */
+enum { DGM_BF16 = 2, DGM_F16 = 3 };
 
 enum {
   DGM_OK = 0,
@@ -124,6 +126,19 @@ int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const vo
  * FP64 on the device; synchronises the stream. */
 int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
                     hipStream_t stream);
+
+/* Dense reference-operator variant on the matrix cores.  The same semi-discrete
+ * operator as dgm_apply_curl / dgm_step, applied as the dense O(N^2) element
+ * matrices that Section 3.2 avoids (curl in the derivative frame, four trace
+ * tables and their transposes), batched over tiles of 64 elements with prec =
+ * DGM_BF16 or DGM_F16 operands and FP32 accumulation (v_mfma_f32_32x32x16).
+ * Fields are FP32 (3, N, K) covariant arrays as above; the field update is FP32.
+ * Results differ from the FP32 path by the 16-bit rounding of the operands
+ * (about 1e-3 relative for BF16, 1e-4 for FP16).  The first call for an order
+ * builds the dense operators (host, then a device copy kept in the handle). */
+int dgm_apply_curl_dense(dgm_mesh* mesh, int prec, const float* E, const float* H, float* dE, float* dH,
+                         hipStream_t stream);
+int dgm_step_dense(dgm_mesh* mesh, int prec, float* E, float* H, double dt, int64_t nsteps, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -40,7 +40,8 @@ def _compile(src, obj):
 
 
 def _newest_header():
-    paths = [os.path.join(CSRC, "launch.h"), os.path.join(HERE, "..", "include", "dgmax.h"), os.path.join(GEN, "frame.inc")]
+    paths = [os.path.join(CSRC, "launch.h"), os.path.join(CSRC, "dense.h"), os.path.join(HERE, "..", "include", "dgmax.h"),
+             os.path.join(GEN, "frame.inc"), os.path.join(GEN, "tables.inc")]
     return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
 
 
@@ -51,7 +52,7 @@ def build(orders=None, jobs=None, force=False, verbose=True):
     orders = list(orders or range(1, tables.P_MAX + 1))
     units = emit.emit_all(GEN, orders)
     os.makedirs(OBJ, exist_ok=True)
-    srcs = [os.path.join(CSRC, "dgmax.hip")] + units
+    srcs = [os.path.join(CSRC, "dgmax.hip"), os.path.join(CSRC, "dense.hip")] + units
     objs = [os.path.join(OBJ, os.path.basename(s).replace(".hip", ".o")) for s in srcs]
     if force:
         for o in objs:

@@ -1,0 +1,330 @@
+// Dense reference-operator variant of one leapfrog phase on the matrix cores.
+//
+// The same operator as the sparse phase kernels, written as three dense
+// matrices that act on a tile of 64 elements at once (one element per GEMM
+// column), with 16-bit operands (BF16 or FP16) and FP32 accumulation on
+// v_mfma_f32_32x32x16_{bf16,f16}:
+//   AT   [8 NF x 3N]        own tangential traces   tau_{f,k} = T_f (g_{f,k} . w)
+//   ATg  [2 NF x 3N] x 4    neighbour traces on the neighbour's face g
+//   AU   [3N x (3N + 8NF)]  curl in the derivative frame plus the lifted jumps
+// where w = M S is the element's field in the derivative frame.  Section 3.2
+// evaluates these operators with O(N) recurrences; this variant applies them
+// as the O(N^2) matrix-vector products the paper avoids, batched over elements
+// so that they run on the matrix cores.  The field update itself stays FP32.
+//
+// Two kernels per phase: dense_trace writes the trace jumps (neighbour minus
+// own, FP32) to a scratch buffer J (8 NF x K); dense_update reads w and J and
+// adds sdt * (A_U [w; J]) to the updated field.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
+#include "generated/tables.inc"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kTile = 64;      // elements per workgroup (two 32-wide MFMA column tiles)
+constexpr int kThreads = 256;  // four waves
+constexpr int kPad = 8;        // extra 16-bit entries per LDS row
+
+template <typename T> struct Vec8;
+template <> struct Vec8<__bf16> { typedef bf16x8 type; };
+template <> struct Vec8<_Float16> { typedef f16x8 type; };
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma(f16x8 a, f16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// Tile of 64 elements: rows rt*32.. of A (row-major, lda = KP) times the LDS
+// operand Bs (element-major rows of stride KP + kPad).  Calls out(row, col, v)
+// for the 32 x 64 result block owned by this lane.
+template <typename T, typename Out>
+__device__ __forceinline__ void gemm_rowtile(const T* __restrict__ A, int KP, const T* Bs, int rt, Out out) {
+  typedef typename Vec8<T>::type V8;
+  const int l = threadIdx.x & 63;
+  const int half = l >> 5, r = l & 31;
+  f32x16 acc0 = {}, acc1 = {};
+  const T* arow = A + (size_t)(rt * 32 + r) * KP + half * 8;
+  const T* b0 = Bs + (size_t)r * (KP + kPad) + half * 8;
+  const T* b1 = Bs + (size_t)(32 + r) * (KP + kPad) + half * 8;
+  for (int ks = 0; ks < KP; ks += 16) {
+    const V8 a = *reinterpret_cast<const V8*>(arow + ks);
+    const V8 x0 = *reinterpret_cast<const V8*>(b0 + ks);
+    const V8 x1 = *reinterpret_cast<const V8*>(b1 + ks);
+    acc0 = mfma(a, x0, acc0);
+    acc1 = mfma(a, x1, acc1);
+  }
+  for (int i = 0; i < 16; ++i) {
+    const int row = rt * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
+    out(row, r, acc0[i]);
+    out(row, 32 + r, acc1[i]);
+  }
+}
+
+// Fill one LDS row block with w = scale * M S of the given elements (16-bit).
+template <typename T>
+__device__ void fill_w(T* Bs, int KP, const float* __restrict__ U, const float* __restrict__ MU, int N, int K,
+                       const int* src, const float* scale, int col0) {
+  const size_t Ks = (size_t)K;
+  for (int idx = threadIdx.x; idx < N * kTile; idx += kThreads) {
+    const int a = idx / kTile, j = idx % kTile;
+    const int e = src[j];
+    float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+    if (e >= 0) {
+      const float s0 = U[(size_t)a * Ks + e], s1 = U[(size_t)(N + a) * Ks + e], s2 = U[(size_t)(2 * N + a) * Ks + e];
+      const float m00 = MU[0 * Ks + e], m01 = MU[1 * Ks + e], m02 = MU[2 * Ks + e];
+      const float m11 = MU[3 * Ks + e], m12 = MU[4 * Ks + e], m22 = MU[5 * Ks + e];
+      const float c = scale[j];
+      w0 = c * (m00 * s0 + m01 * s1 + m02 * s2);
+      w1 = c * (m01 * s0 + m11 * s1 + m12 * s2);
+      w2 = c * (m02 * s0 + m12 * s1 + m22 * s2);
+    }
+    T* row = Bs + (size_t)j * (KP + kPad) + col0;
+    row[a] = (T)w0;
+    row[N + a] = (T)w1;
+    row[2 * N + a] = (T)w2;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dense_trace_kernel(const float* __restrict__ U, const float* __restrict__ MU,
+                                                               const int* __restrict__ nbr, float wall, int K, int N,
+                                                               int NF, int KP, const T* __restrict__ AT,
+                                                               const T* __restrict__ ATg, float* __restrict__ J) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Bs = reinterpret_cast<T*>(smem);
+  __shared__ int src[kTile];
+  __shared__ float scl[kTile];
+  __shared__ int gface[kTile];
+  const int wave = threadIdx.x >> 6;
+  const int e0 = blockIdx.x * kTile;
+  const size_t Ks = (size_t)K;
+  // own field; zero the padding columns once
+  if (threadIdx.x < kTile) {
+    const int e = e0 + threadIdx.x;
+    src[threadIdx.x] = e < K ? e : -1;
+    scl[threadIdx.x] = 1.f;
+  }
+  for (int idx = threadIdx.x; idx < kTile * (KP + kPad - 3 * N); idx += kThreads) {
+    const int j = idx / (KP + kPad - 3 * N), c = 3 * N + idx % (KP + kPad - 3 * N);
+    Bs[(size_t)j * (KP + kPad) + c] = (T)0.f;
+  }
+  __syncthreads();
+  fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
+  __syncthreads();
+  const int M1 = 8 * NF;
+  for (int rt = wave; rt * 32 < M1; rt += 4)
+    gemm_rowtile<T>(AT, KP, Bs, rt, [&](int row, int col, float v) {
+      const int e = e0 + col;
+      if (row < M1 && e < K) J[(size_t)row * Ks + e] = -v;
+    });
+  const int M2 = 2 * NF;
+  for (int f = 0; f < 4; ++f) {
+    __syncthreads();
+    if (threadIdx.x < kTile) {
+      const int e = e0 + threadIdx.x;
+      int s = -1, g = f;
+      float c = 1.f;
+      if (e < K) {
+        const int code = nbr[(size_t)f * Ks + e];
+        if (code < 0) {
+          s = e;  // wall: ghost trace = wall * own trace on the same face
+          c = wall;
+        } else {
+          s = code >> 2;
+          g = code & 3;
+        }
+      }
+      src[threadIdx.x] = s;
+      scl[threadIdx.x] = c;
+      gface[threadIdx.x] = g;
+    }
+    __syncthreads();
+    fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
+    __syncthreads();  // also orders this tile's own-trace stores to J before the updates below
+    int present = 0;
+    for (int j = 0; j < kTile; ++j) present |= 1 << gface[j];
+    for (int g = 0; g < 4; ++g) {
+      if (!(present & (1 << g))) continue;
+      const T* A = ATg + (size_t)g * rup(M2, 32) * KP;
+      for (int rt = wave; rt * 32 < M2; rt += 4)
+        gemm_rowtile<T>(A, KP, Bs, rt, [&](int row, int col, float v) {
+          const int e = e0 + col;
+          if (row < M2 && e < K && gface[col] == g) J[(size_t)(f * M2 + row) * Ks + e] += v;
+        });
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __restrict__ U, float* __restrict__ V,
+                                                                const float* __restrict__ MU,
+                                                                const float* __restrict__ J, float sdt, int K, int N,
+                                                                int NF, int KP, const T* __restrict__ AU) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Bs = reinterpret_cast<T*>(smem);
+  __shared__ int src[kTile];
+  __shared__ float scl[kTile];
+  const int wave = threadIdx.x >> 6;
+  const int e0 = blockIdx.x * kTile;
+  const size_t Ks = (size_t)K;
+  if (threadIdx.x < kTile) {
+    const int e = e0 + threadIdx.x;
+    src[threadIdx.x] = e < K ? e : -1;
+    scl[threadIdx.x] = 1.f;
+  }
+  const int c0 = 3 * N + 8 * NF;
+  for (int idx = threadIdx.x; idx < kTile * (KP + kPad - c0); idx += kThreads) {
+    const int j = idx / (KP + kPad - c0), c = c0 + idx % (KP + kPad - c0);
+    Bs[(size_t)j * (KP + kPad) + c] = (T)0.f;
+  }
+  __syncthreads();
+  fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
+  for (int idx = threadIdx.x; idx < 8 * NF * kTile; idx += kThreads) {
+    const int q = idx / kTile, j = idx % kTile;
+    const int e = e0 + j;
+    Bs[(size_t)j * (KP + kPad) + 3 * N + q] = (T)(e < K ? J[(size_t)q * Ks + e] : 0.f);
+  }
+  __syncthreads();
+  const int M3 = 3 * N;
+  for (int rt = wave; rt * 32 < M3; rt += 4)
+    gemm_rowtile<T>(AU, KP, Bs, rt, [&](int row, int col, float v) {
+      const int e = e0 + col;
+      if (row < M3 && e < K) V[(size_t)row * Ks + e] += sdt * v;
+    });
+}
+
+uint16_t to_bf16(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)((u + rounding) >> 16);
+}
+
+uint16_t to_f16(double x) {
+  const _Float16 h = (_Float16)(float)x;
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+}  // namespace
+
+struct DenseOps {
+  int p = 0, prec = 0, N = 0, NF = 0, KP1 = 0, KP2 = 0;
+  void* AT = nullptr;
+  void* ATg = nullptr;
+  void* AU = nullptr;
+};
+
+int dense_build(int p, int prec, DenseOps** out, const char** err) {
+  *out = nullptr;
+  if (p < 1 || p > (int)(sizeof(kTables) / sizeof(kTables[0])) - 1) {
+    *err = "order out of range for the dense variant";
+    return -1;
+  }
+  const OrderTables& t = kTables[p];
+  const int N = t.N, NF = t.NF;
+  const int KP1 = rup(3 * N, 16), KP2 = rup(3 * N + 8 * NF, 16);
+  const int M1P = rup(8 * NF, 32), M2P = rup(2 * NF, 32), M3P = rup(3 * N, 32);
+  std::vector<double> AT((size_t)M1P * KP1, 0.0), ATg((size_t)4 * M2P * KP1, 0.0), AU((size_t)M3P * KP2, 0.0);
+  for (int f = 0; f < 4; ++f)
+    for (int q = 0; q < t.nT[f]; ++q) {
+      const SparseEntry& s = t.T[f][q];
+      for (int k = 0; k < 2; ++k)
+        for (int c = 0; c < 3; ++c) {
+          AT[(size_t)((f * 2 + k) * NF + s.r) * KP1 + c * N + s.c] += t.g[f][k][c] * s.v;
+          ATg[((size_t)f * M2P + k * NF + s.r) * KP1 + c * N + s.c] += t.g[f][k][c] * s.v;
+        }
+      for (int k = 0; k < 3; ++k)
+        for (int sc = 0; sc < 2; ++sc)
+          AU[(size_t)(k * N + s.c) * KP2 + 3 * N + (f * 2 + sc) * NF + s.r] += t.Lp[f][k][sc] * s.v;
+    }
+  static const int cyc[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+  for (int k = 0; k < 3; ++k) {
+    const int i = cyc[k][0], j = cyc[k][1];
+    for (int q = 0; q < t.nD[i]; ++q) {  // + D_i w_j
+      const SparseEntry& s = t.D[i][q];
+      AU[(size_t)(k * N + s.r) * KP2 + j * N + s.c] += s.v;
+    }
+    for (int q = 0; q < t.nD[j]; ++q) {  // - D_j w_i
+      const SparseEntry& s = t.D[j][q];
+      AU[(size_t)(k * N + s.r) * KP2 + i * N + s.c] -= s.v;
+    }
+  }
+  auto conv = [&](const std::vector<double>& src, void** dst) -> int {
+    std::vector<uint16_t> h(src.size());
+    for (size_t q = 0; q < src.size(); ++q) h[q] = prec == 0 ? to_bf16(src[q]) : to_f16(src[q]);
+    if (hipMalloc(dst, h.size() * 2) != hipSuccess) return -5;
+    if (hipMemcpy(*dst, h.data(), h.size() * 2, hipMemcpyHostToDevice) != hipSuccess) return -6;
+    return 0;
+  };
+  auto* d = new DenseOps();
+  d->p = p;
+  d->prec = prec;
+  d->N = N;
+  d->NF = NF;
+  d->KP1 = KP1;
+  d->KP2 = KP2;
+  int rc = conv(AT, &d->AT);
+  if (!rc) rc = conv(ATg, &d->ATg);
+  if (!rc) rc = conv(AU, &d->AU);
+  if (rc) {
+    dense_free(d);
+    *err = "device allocation for the dense operators failed";
+    return rc;
+  }
+  *out = d;
+  return 0;
+}
+
+void dense_free(DenseOps* d) {
+  if (!d) return;
+  (void)hipFree(d->AT);
+  (void)hipFree(d->ATg);
+  (void)hipFree(d->AU);
+  delete d;
+}
+
+size_t dense_scratch_floats(const DenseOps* d, int64_t K) { return (size_t)8 * d->NF * (size_t)K; }
+
+template <typename T>
+static hipError_t dense_phase_t(const DenseOps* d, const float* U, float* V, const float* MU, const int* nbr,
+                                float sdt, float wall, int K, float* J, hipStream_t s) {
+  const int blocks = (K + kTile - 1) / kTile;
+  const size_t lds1 = (size_t)kTile * (d->KP1 + kPad) * sizeof(T);
+  const size_t lds2 = (size_t)kTile * (d->KP2 + kPad) * sizeof(T);
+  hipError_t e = hipFuncSetAttribute((const void*)dense_trace_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds1);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)dense_update_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dense_trace_kernel<T>, dim3(blocks), dim3(kThreads), lds1, s, U, MU, nbr, wall, K, d->N, d->NF,
+                     d->KP1, (const T*)d->AT, (const T*)d->ATg, J);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dense_update_kernel<T>, dim3(blocks), dim3(kThreads), lds2, s, U, V, MU, (const float*)J, sdt, K,
+                     d->N, d->NF, d->KP2, (const T*)d->AU);
+  return hipGetLastError();
+}
+
+hipError_t dense_phase(const DenseOps* d, const float* U, float* V, const float* MU, const int* nbr, float sdt,
+                       float wall, int K, float* J, hipStream_t s) {
+  return d->prec == 0 ? dense_phase_t<__bf16>(d, U, V, MU, nbr, sdt, wall, K, J, s)
+                      : dense_phase_t<_Float16>(d, U, V, MU, nbr, sdt, wall, K, J, s);
+}

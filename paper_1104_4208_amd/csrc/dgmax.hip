@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/dgmax.h"
+#include "dense.h"
 #include "launch.h"
 #include "generated/frame.inc"
 
@@ -175,6 +176,10 @@ struct dgm_mesh {
   size_t scratch_bytes = 0;
   double* d_partial = nullptr;
   int partial_n = 0;
+  // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
+  DenseOps* dense[2] = {nullptr, nullptr};
+  float* d_jump = nullptr;
+  size_t jump_floats = 0;
 };
 
 namespace {
@@ -417,6 +422,43 @@ int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, dou
   return DGM_OK;
 }
 
+
+int dense_ready(dgm_mesh* m, int prec, DenseOps** out) {
+  const int q = prec == DGM_BF16 ? 0 : 1;
+  if (!m->dense[q]) {
+    const char* err = "";
+    const int rc = dense_build(m->p, q, &m->dense[q], &err);
+    if (rc) return fail(rc == -1 ? DGM_ERR_ARG : (rc == -5 ? DGM_ERR_OOM : DGM_ERR_HIP), err);
+  }
+  const size_t need = dense_scratch_floats(m->dense[q], m->K);
+  if (m->jump_floats < need) {
+    if (m->d_jump) HIP_TRY(hipFree(m->d_jump));
+    m->d_jump = nullptr;
+    m->jump_floats = 0;
+    HIP_TRY(hipMalloc(&m->d_jump, need * sizeof(float)));
+    m->jump_floats = need;
+  }
+  *out = m->dense[q];
+  return DGM_OK;
+}
+
+int run_dense_phase(dgm_mesh* m, DenseOps* d, const float* U, float* V, int fld_u, double sdt, hipStream_t s) {
+  HIP_TRY(dense_phase(d, U, V, m->d_M32[fld_u], m->d_nbr, (float)sdt, fld_u == 0 ? -1.f : 1.f, (int)m->K, m->d_jump, s));
+  return DGM_OK;
+}
+
+int dense_rate(dgm_mesh* m, DenseOps* d, const float* in, float* out, int fld_u, hipStream_t s) {
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  int rc;
+  if ((rc = ensure_scratch(m, n * sizeof(float)))) return rc;
+  float* tmp = static_cast<float*>(m->d_scratch);
+  HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if ((rc = convert<float>(m, tmp, fld_u, true, s))) return rc;
+  if ((rc = fill<float>(out, n, 0.f, s))) return rc;
+  if ((rc = run_dense_phase(m, d, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, s))) return rc;
+  return convert<float>(m, out, 1 - fld_u, false, s);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C-ABI
@@ -553,6 +595,9 @@ int dgm_destroy(dgm_mesh* m) {
   }
   hipFree(m->d_scratch);
   hipFree(m->d_partial);
+  dense_free(m->dense[0]);
+  dense_free(m->dense[1]);
+  hipFree(m->d_jump);
   delete m;
   return DGM_OK;
 }
@@ -566,6 +611,12 @@ int dgm_num_elements(const dgm_mesh* m, int64_t* K) {
 int dgm_set_order(dgm_mesh* m, int p) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
   if (p < 1 || p > DGM_MAX_ORDER_F32) return fail(DGM_ERR_ARG, "order out of range");
+  if (m->p != p) {
+    for (int q = 0; q < 2; ++q) {
+      dense_free(m->dense[q]);
+      m->dense[q] = nullptr;
+    }
+  }
   m->p = p;
   return DGM_OK;
 }
@@ -646,6 +697,37 @@ int dgm_estimate_dt(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* d
   if (rho_out) *rho_out = rho;
   *dt = cfl * 2.0 / std::sqrt(rho);
   return DGM_OK;
+}
+
+int dgm_apply_curl_dense(dgm_mesh* m, int prec, const float* E, const float* H, float* dE, float* dH, hipStream_t s) {
+  int rc = check_order(m, DGM_F32);
+  if (rc) return rc;
+  if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
+  if ((dH && !E) || (dE && !H)) return fail(DGM_ERR_ARG, "output requested without its input");
+  if ((dH && (dH == E || dH == H)) || (dE && (dE == E || dE == H))) return fail(DGM_ERR_ARG, "outputs alias inputs");
+  DenseOps* d = nullptr;
+  if ((rc = dense_ready(m, prec, &d))) return rc;
+  if (dH && (rc = dense_rate(m, d, E, dH, 0, s))) return rc;
+  if (dE && (rc = dense_rate(m, d, H, dE, 1, s))) return rc;
+  return DGM_OK;
+}
+
+int dgm_step_dense(dgm_mesh* m, int prec, float* E, float* H, double dt, int64_t nsteps, hipStream_t s) {
+  int rc = check_order(m, DGM_F32);
+  if (rc) return rc;
+  if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
+  if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
+  if (nsteps == 0) return DGM_OK;
+  DenseOps* d = nullptr;
+  if ((rc = dense_ready(m, prec, &d))) return rc;
+  if ((rc = convert<float>(m, E, 0, true, s))) return rc;
+  if ((rc = convert<float>(m, H, 1, true, s))) return rc;
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if ((rc = run_dense_phase(m, d, E, H, 0, -dt, s))) return rc;
+    if ((rc = run_dense_phase(m, d, H, E, 1, dt, s))) return rc;
+  }
+  if ((rc = convert<float>(m, E, 0, false, s))) return rc;
+  return convert<float>(m, H, 1, false, s);
 }
 
 }  // extern "C"

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgmax.so")
 
 DGM_F32, DGM_F64 = 0, 1
+DGM_BF16, DGM_F16 = 2, 3
 ERRORS = {
     -1: "DGM_ERR_ARG", -2: "DGM_ERR_MESH_DEGENERATE", -3: "DGM_ERR_MESH_NONMANIFOLD", -4: "DGM_ERR_MATERIAL",
     -5: "DGM_ERR_OOM", -6: "DGM_ERR_HIP", -7: "DGM_ERR_UNSTABLE", -8: "DGM_ERR_STATE",
@@ -46,6 +47,8 @@ SIGNATURES = {
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
     "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
     "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
+    "dgm_apply_curl_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "dgm_step_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
 }
 
 _lib = None
@@ -214,6 +217,30 @@ class Mesh:
         _check(load_library().dgm_energy(self._h, _dtype_code(E), _ptr(E), _ptr(H), _ptr(Hn), float(dt), out,
                                          _stream()))
         return out[0], out[1]
+
+    def apply_curl_dense(self, E=None, H=None, prec: int = DGM_BF16, dE=None, dH=None):
+        """Dense matrix-core variant of apply_curl (FP32 fields, 16-bit operands)."""
+        E, H = self._field(E, "E"), self._field(H, "H")
+        torch = _torch()
+        for t in (E, H):
+            if t is not None and t.dtype != torch.float32:
+                raise DGMError("the dense variant takes float32 fields")
+        if H is not None and dE is None:
+            dE = torch.empty_like(H)
+        if E is not None and dH is None:
+            dH = torch.empty_like(E)
+        _check(load_library().dgm_apply_curl_dense(
+            self._h, int(prec), _ptr(E), _ptr(H), _ptr(dE if H is not None else None),
+            _ptr(dH if E is not None else None), _stream()))
+        return (dE if H is not None else None), (dH if E is not None else None)
+
+    def step_dense(self, E, H, dt: float, nsteps: int = 1, prec: int = DGM_BF16):
+        E, H = self._field(E, "E"), self._field(H, "H")
+        torch = _torch()
+        if E.dtype != torch.float32 or H.dtype != torch.float32:
+            raise DGMError("the dense variant takes float32 fields")
+        _check(load_library().dgm_step_dense(self._h, int(prec), _ptr(E), _ptr(H), float(dt), int(nsteps), _stream()))
+        return E, H
 
     def estimate_dt(self, cfl: float = 0.5, iters: int = 50, seed: int = 1):
         dt, rho = ctypes.c_double(), ctypes.c_double()

@@ -605,4 +605,38 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     lines.append("static hipError_t (*const kPhaseF32[])(const PhaseArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f32" for p in orders) + "};")
     lines.append("static hipError_t (*const kPhaseF64[])(const PhaseArgs<double>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f64" for p in orders if p <= F64_MAX_ORDER) + "};")
     _write_if_changed(os.path.join(outdir, "frame.inc"), "\n".join(lines) + "\n")
+    _write_if_changed(os.path.join(outdir, "tables.inc"), emit_host_tables(orders))
     return units
+
+
+def emit_host_tables(orders):
+    """Sparse reference tables for the host (dense-operator assembly at set-up):
+    per order the derivative operators D0..D2 and trace operators T0..T3 as
+    (row, col, value) triplets, the tangential weights g[f][k] and the stored-frame
+    lift weights Lp[f][k][s]."""
+    L = ["// Generated by gen/emit.py: sparse reference tables for host-side assembly.",
+         "struct SparseEntry { short r, c; double v; };",
+         "struct OrderTables { int N, NF; const SparseEntry* D[3]; int nD[3]; const SparseEntry* T[4]; int nT[4];",
+         "                     double g[4][2][3]; double Lp[4][3][2]; };"]
+    for p in orders:
+        t = TB.build(p)
+        g, Lp = TB.face_weights(t)
+        for d in range(3):
+            r, c = np.nonzero(t.D[d])
+            L.append(f"static const SparseEntry kD{d}_p{p}[] = {{" + ", ".join(f"{{{i},{j},{float(t.D[d][i, j]).hex()}}}" for i, j in zip(r, c)) + "};")
+        for f in range(4):
+            r, c = np.nonzero(t.T[f])
+            L.append(f"static const SparseEntry kT{f}_p{p}[] = {{" + ", ".join(f"{{{i},{j},{float(t.T[f][i, j]).hex()}}}" for i, j in zip(r, c)) + "};")
+    L.append("static const OrderTables kTables[] = {")
+    L.append("  {0, 0, {nullptr, nullptr, nullptr}, {0, 0, 0}, {nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, {}, {}},")
+    for p in orders:
+        t = TB.build(p)
+        g, Lp = TB.face_weights(t)
+        nD = [int(np.count_nonzero(t.D[d])) for d in range(3)]
+        nT = [int(np.count_nonzero(t.T[f])) for f in range(4)]
+        gs = "{" + ", ".join("{" + ", ".join("{" + ", ".join(float(v).hex() for v in g[f][k]) + "}" for k in range(2)) + "}" for f in range(4)) + "}"
+        ls = "{" + ", ".join("{" + ", ".join("{" + ", ".join(float(v).hex() for v in Lp[f][k]) + "}" for k in range(3)) + "}" for f in range(4)) + "}"
+        L.append(f"  {{{t.N}, {t.NF}, {{kD0_p{p}, kD1_p{p}, kD2_p{p}}}, {{{nD[0]}, {nD[1]}, {nD[2]}}}, "
+                 f"{{kT0_p{p}, kT1_p{p}, kT2_p{p}, kT3_p{p}}}, {{{nT[0]}, {nT[1]}, {nT[2]}, {nT[3]}}}, {gs}, {ls}}},")
+    L.append("};")
+    return "\n".join(L) + "\n"
