@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-dense", action="store_true", help="skip the p=8 dense matrix-core comparison")
     ap.add_argument("--dense-steps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-nmax", type=int, default=10)
     return ap.parse_args()
 
 
@@ -238,6 +241,14 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_dense:
         out["dense_variant"] = dense_comparison(a.dense_steps)
+    if not a.no_serve:
+        from paper_1104_4208_amd import serve
+
+        rep = serve.serve_report(num=a.serve_requests, budget_gib=2.0, chunk=20, n_range=(4, a.serve_nmax))
+        rep["note"] = ("reduced trace of the serving workload (same recipe: Poisson arrivals at 50/s, p in 2..8, "
+                       "eps in {1,2,4}, steps in 200..2000, jitter 0.1 h) with n <= serve_nmax so the default run stays "
+                       "short; `python -m paper_1104_4208_amd.serve` runs the full 256-request trace")
+        out["serving"] = rep
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)

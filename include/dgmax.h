@@ -113,8 +113,10 @@ int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nst
 /* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),
  * out[1] = Q = 1/2 (E, M_eps E) + 1/2 (H, M_mu H_next), the quantity the
  * H-first symplectic Euler step conserves exactly.  H_next is the H of the next
- * step; if NULL it is computed internally as H + dt dH(E).  Returns
- * DGM_ERR_UNSTABLE if W or Q is not finite (out is still written). */
+ * step; if NULL it is computed internally as H + dt dH(E) (H itself when dt is
+ * 0, so Q = W).  The reductions run at any order; forming H_next needs the
+ * order compiled for dtype.  Returns DGM_ERR_UNSTABLE if W or Q is not finite
+ * (out is still written). */
 int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const void* H_next, double dt,
                double out[2], hipStream_t stream);
 
@@ -123,7 +125,8 @@ int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const vo
  * [-1,1)) estimates rho = rho(M_mu^{-1/2} C M_eps^{-1} C^T M_mu^{-1/2}); the
  * result is dt = cfl * 2 / sqrt(rho) (the printed bound lacks the square root;
  * leapfrog is stable iff dt <= 2/sqrt(rho)).  rho_out may be NULL.  Runs in
- * FP64 on the device; synchronises the stream. */
+ * FP64 on the device where the order is compiled in FP64 (dgm_max_order), in
+ * FP32 with FP64 dot products above it; synchronises the stream. */
 int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
                     hipStream_t stream);
 
@@ -139,6 +142,28 @@ int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double
 int dgm_apply_curl_dense(dgm_mesh* mesh, int prec, const float* E, const float* H, float* dE, float* dH,
                          hipStream_t stream);
 int dgm_step_dense(dgm_mesh* mesh, int prec, float* E, float* H, double dt, int64_t nsteps, hipStream_t stream);
+
+/* Batched serving: many independent solves advance together.  A batch holds
+ * slots (mesh handle, caller-owned FP32 E and H, dt, remaining steps).  Each
+ * dgm_batch_advance advances every active slot by min(chunk, remaining) steps
+ * with one HIP-graph launch whose kernels (one per order and half step) cover
+ * all slots of that order; finished slots are converted back to the covariant
+ * layout and reported by dgm_batch_take_finished.  Between dgm_batch_add and
+ * completion, E and H hold the library's internal stored-frame coefficients
+ * and must not be read or written by the caller.  A mesh handle may back at
+ * most one active slot.  Results are bitwise equal to dgm_step on the same
+ * slot alone (same kernels, same per-element arithmetic).  Not part of the
+ * paper (its solver runs one mesh on one core); this is the serving layer. */
+typedef struct dgm_batch dgm_batch;
+int dgm_batch_create(int chunk, dgm_batch** out);
+int dgm_batch_destroy(dgm_batch* batch);
+int dgm_batch_add(dgm_batch* batch, dgm_mesh* mesh, float* E, float* H, double dt, int64_t nsteps,
+                  hipStream_t stream, int64_t* id);
+int dgm_batch_num_active(const dgm_batch* batch, int64_t* n);
+/* Advances all active slots and synchronises the stream. */
+int dgm_batch_advance(dgm_batch* batch, hipStream_t stream);
+/* Copies up to cap finished slot ids into ids and removes them from the list. */
+int dgm_batch_take_finished(dgm_batch* batch, int64_t* ids, int64_t cap, int64_t* n);
 
 #ifdef __cplusplus
 }

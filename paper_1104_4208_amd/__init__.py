@@ -7,5 +7,5 @@
 Everything runs in libdgmax.so (C-ABI in include/dgmax.h); this package only
 marshals arguments.  Build the library with ``python -m paper_1104_4208_amd.build``.
 """
-from .dgmax import (DGM_BF16, DGM_F16, DGM_F32, DGM_F64, DGMError, Mesh, load_library, max_order, mode_index,  # noqa: F401
+from .dgmax import (DGM_BF16, DGM_F16, DGM_F32, DGM_F64, Batch, DGMError, Mesh, load_library, max_order, mode_index,  # noqa: F401
                     mode_table, num_face_modes, num_modes)

@@ -141,19 +141,21 @@ __global__ void __launch_bounds__(kRedThreads) final_sum_kernel(const double* __
 
 // SplitMix64 (Steele, Lea, Flood 2014) mapped to [-1, 1): start vector of the
 // power iteration, identical to the host reference generator.
-__global__ void splitmix_fill_kernel(double* __restrict__ X, size_t n, unsigned long long seed) {
+template <typename R>
+__global__ void splitmix_fill_kernel(R* __restrict__ X, size_t n, unsigned long long seed) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   z = z ^ (z >> 31);
-  X[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  X[i] = (R)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
 }
 
-__global__ void scale_kernel(double* __restrict__ X, size_t n, const double* __restrict__ d) {
+template <typename R>
+__global__ void scale_kernel(R* __restrict__ X, size_t n, const double* __restrict__ d) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) X[i] = -X[i] / sqrt(*d);
+  if (i < n) X[i] = (R)(-(double)X[i] / sqrt(*d));
 }
 
 }  // namespace
@@ -459,6 +461,48 @@ int dense_rate(dgm_mesh* m, DenseOps* d, const float* in, float* out, int fld_u,
   return convert<float>(m, out, 1 - fld_u, false, s);
 }
 
+
+template <typename R>
+int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
+  int rc = DGM_OK;
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  R* x = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), 3 * n * sizeof(R) + 5 * sizeof(double), s));
+  R* const base = x;
+  R* y = x + n;
+  R* z = y + n;
+  // three FP64 dot products after the vectors, aligned to 8 bytes
+  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(z + n) + 7) & ~uintptr_t(7));
+  const int threads = 256;
+  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+  hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(threads), 0, s, x, n, (unsigned long long)seed);
+  HIP_TRY(hipGetLastError());
+  for (int it = 0; it < iters && !rc; ++it) {
+    // z = dH(dE(x)) = -B x, where B = M_mu^{-1} C M_eps^{-1} C^T is similar to the
+    // symmetric matrix of the bound; Rayleigh quotient in the M_mu inner product
+    if ((rc = rate_impl<R>(m, x, y, 1, s))) break;
+    if ((rc = rate_impl<R>(m, y, z, 0, s))) break;
+    if ((rc = mdot<R>(m, x, z, 1, d + 0, s))) break;
+    if ((rc = mdot<R>(m, x, x, 1, d + 1, s))) break;
+    if ((rc = mdot<R>(m, z, z, 1, d + 2, s))) break;
+    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(threads), 0, s, z, n, d + 2);
+    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
+    std::swap(x, z);
+  }
+  double h[3] = {0, 0, 0};
+  if (!rc) {
+    HIP_TRY(hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipFreeAsync(base, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rc) return rc;
+  const double rho = -h[0] / h[1];
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
+  if (rho_out) *rho_out = rho;
+  *dt = cfl * 2.0 / std::sqrt(rho);
+  return DGM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C-ABI
@@ -651,52 +695,26 @@ int dgm_step(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps
 
 int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void* Hn, double dt, double out[2],
                hipStream_t s) {
-  int rc = check_order(m, dtype);
-  if (rc) return rc;
+  // The reductions work at any order; only forming H_next internally needs the
+  // order's phase kernel.
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  if (dtype != DGM_F32 && dtype != DGM_F64) return fail(DGM_ERR_ARG, "dtype must be DGM_F32 or DGM_F64");
+  if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
   if (!E || !H || !out) return fail(DGM_ERR_ARG, "null argument");
+  if (!Hn && dt == 0.0) Hn = H;  // Q = W when no step is taken
+  int rc;
+  if (!Hn && (rc = check_order(m, dtype))) return rc;
   return dtype == DGM_F32 ? energy_impl<float>(m, (const float*)E, (const float*)H, (const float*)Hn, dt, out, s)
                           : energy_impl<double>(m, (const double*)E, (const double*)H, (const double*)Hn, dt, out, s);
 }
 
 int dgm_estimate_dt(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
-  int rc = check_order(m, DGM_F64);
+  int rc = check_order(m, DGM_F32);
   if (rc) return rc;
   if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
-  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
-  double* x = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), 3 * n * sizeof(double) + 4 * sizeof(double), s));
-  double* const base = x;
-  double* y = x + n;
-  double* z = y + n;
-  double* d = z + n;
-  const int threads = 256;
-  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
-  hipLaunchKernelGGL(splitmix_fill_kernel, dim3(blocks), dim3(threads), 0, s, x, n, (unsigned long long)seed);
-  HIP_TRY(hipGetLastError());
-  for (int it = 0; it < iters && !rc; ++it) {
-    // z = dH(dE(x)) = -B x, where B = M_mu^{-1} C M_eps^{-1} C^T is similar to the
-    // symmetric matrix of the bound; Rayleigh quotient in the M_mu inner product
-    if ((rc = rate_impl<double>(m, x, y, 1, s))) break;
-    if ((rc = rate_impl<double>(m, y, z, 0, s))) break;
-    if ((rc = mdot<double>(m, x, z, 1, d + 0, s))) break;
-    if ((rc = mdot<double>(m, x, x, 1, d + 1, s))) break;
-    if ((rc = mdot<double>(m, z, z, 1, d + 2, s))) break;
-    hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(threads), 0, s, z, n, d + 2);
-    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
-    std::swap(x, z);
-  }
-  double h[3] = {0, 0, 0};
-  if (!rc) {
-    HIP_TRY(hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipFreeAsync(base, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (rc) return rc;
-  const double rho = -h[0] / h[1];
-  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
-  if (rho_out) *rho_out = rho;
-  *dt = cfl * 2.0 / std::sqrt(rho);
-  return DGM_OK;
+  // FP64 vectors where the order is compiled in FP64, FP32 vectors (FP64 dots) above it
+  return m->p <= DGM_MAX_ORDER_F64 ? estimate_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
+                                   : estimate_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
 }
 
 int dgm_apply_curl_dense(dgm_mesh* m, int prec, const float* E, const float* H, float* dE, float* dH, hipStream_t s) {
@@ -728,6 +746,200 @@ int dgm_step_dense(dgm_mesh* m, int prec, float* E, float* H, double dt, int64_t
   }
   if ((rc = convert<float>(m, E, 0, false, s))) return rc;
   return convert<float>(m, H, 1, false, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched serving
+// Many meshes (slots) advance together: per order, one batched kernel launch per
+// leapfrog half step covers every slot of that order, and a chunk of steps for all
+// orders is captured once in a HIP graph.  The graph's kernels read the slot
+// tables from device memory, so admitting or retiring a slot only rewrites the
+// tables; the graph is re-captured only when an order needs a larger grid.
+struct dgm_batch {
+  struct Slot {
+    dgm_mesh* m;
+    float* E;
+    float* H;
+    double dt;
+    int64_t left;
+    int64_t id;
+  };
+  int chunk = 0;
+  std::vector<Slot> active;
+  std::vector<int64_t> finished;
+  int64_t next_id = 0;
+  BatchSlot* d_slots[DGM_MAX_ORDER_F32 + 1] = {};
+  int* d_tile0[DGM_MAX_ORDER_F32 + 1] = {};
+  int* d_n[DGM_MAX_ORDER_F32 + 1] = {};
+  int cap_slots[DGM_MAX_ORDER_F32 + 1] = {};
+  int cap_tiles[DGM_MAX_ORDER_F32 + 1] = {};
+  std::vector<BatchSlot> h_slots[DGM_MAX_ORDER_F32 + 1];
+  std::vector<int> h_tile0[DGM_MAX_ORDER_F32 + 1];
+  int h_n[DGM_MAX_ORDER_F32 + 1] = {};
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+};
+
+namespace {
+
+int batch_capture(dgm_batch* b) {
+  if (b->exec) HIP_TRY(hipGraphExecDestroy(b->exec));
+  if (b->graph) HIP_TRY(hipGraphDestroy(b->graph));
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int sub = 0; sub < b->chunk && err == hipSuccess; ++sub)
+    for (int phase = 0; phase < 2 && err == hipSuccess; ++phase)
+      for (int p = 1; p <= DGM_MAX_ORDER_F32 && err == hipSuccess; ++p) {
+        if (b->cap_tiles[p] <= 0) continue;
+        BatchArgs a;
+        a.slots = b->d_slots[p];
+        a.tile0 = b->d_tile0[p];
+        a.nslots = b->d_n[p];
+        a.phase = phase;
+        a.substep = sub;
+        a.blocks = b->cap_tiles[p];
+        a.stream = b->cap_stream;
+        err = kBatchF32[p](a);
+      }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+  if (err != hipSuccess) return fail(DGM_ERR_HIP, std::string("batched launch capture: ") + hipGetErrorString(err));
+  if (e2 != hipSuccess) return fail(DGM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->dirty = false;
+  return DGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgm_batch_create(int chunk, dgm_batch** out) {
+  if (!out || chunk < 1 || chunk > 4096) return fail(DGM_ERR_ARG, "chunk must be in [1, 4096]");
+  *out = new dgm_batch();
+  (*out)->chunk = chunk;
+  return DGM_OK;
+}
+
+int dgm_batch_destroy(dgm_batch* b) {
+  if (!b) return DGM_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (int p = 0; p <= DGM_MAX_ORDER_F32; ++p) {
+    (void)hipFree(b->d_slots[p]);
+    (void)hipFree(b->d_tile0[p]);
+    (void)hipFree(b->d_n[p]);
+  }
+  delete b;
+  return DGM_OK;
+}
+
+int dgm_batch_add(dgm_batch* b, dgm_mesh* m, float* E, float* H, double dt, int64_t nsteps, hipStream_t s,
+                  int64_t* id) {
+  if (!b || !E || !H || E == H || nsteps < 0 || !std::isfinite(dt) || !id) return fail(DGM_ERR_ARG, "bad batch slot");
+  int rc = check_order(m, DGM_F32);
+  if (rc) return rc;
+  for (const auto& q : b->active)
+    if (q.m == m) return fail(DGM_ERR_ARG, "mesh handle already has an active slot");
+  if ((rc = convert<float>(m, E, 0, true, s))) return rc;
+  if ((rc = convert<float>(m, H, 1, true, s))) return rc;
+  *id = b->next_id++;
+  if (nsteps == 0) {
+    if ((rc = convert<float>(m, E, 0, false, s))) return rc;
+    if ((rc = convert<float>(m, H, 1, false, s))) return rc;
+    b->finished.push_back(*id);
+    return DGM_OK;
+  }
+  b->active.push_back({m, E, H, dt, nsteps, *id});
+  return DGM_OK;
+}
+
+int dgm_batch_num_active(const dgm_batch* b, int64_t* n) {
+  if (!b || !n) return fail(DGM_ERR_ARG, "null argument");
+  *n = (int64_t)b->active.size();
+  return DGM_OK;
+}
+
+int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
+  if (!b) return fail(DGM_ERR_ARG, "null batch");
+  if (b->active.empty()) return DGM_OK;
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p) {
+    b->h_slots[p].clear();
+    b->h_tile0[p].assign(1, 0);
+  }
+  for (const auto& q : b->active) {
+    const int p = q.m->p;
+    BatchSlot bs;
+    bs.E = q.E;
+    bs.H = q.H;
+    bs.ME = q.m->d_M32[0];
+    bs.MH = q.m->d_M32[1];
+    bs.nbr = q.m->d_nbr;
+    bs.K = (int)q.m->K;
+    bs.steps_left = (int)std::min<int64_t>(b->chunk, q.left);
+    bs.dt = q.dt;
+    b->h_slots[p].push_back(bs);
+    b->h_tile0[p].push_back(b->h_tile0[p].back() + (int)((q.m->K + 63) / 64));
+  }
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p) {
+    const int ns = (int)b->h_slots[p].size(), nt = b->h_tile0[p].back();
+    if (ns > b->cap_slots[p]) {
+      const int cap = std::max(ns, 2 * b->cap_slots[p]);
+      (void)hipFree(b->d_slots[p]);
+      (void)hipFree(b->d_tile0[p]);
+      b->d_slots[p] = nullptr;
+      b->d_tile0[p] = nullptr;
+      HIP_TRY(hipMalloc(&b->d_slots[p], cap * sizeof(BatchSlot)));
+      HIP_TRY(hipMalloc(&b->d_tile0[p], (cap + 1) * sizeof(int)));
+      if (!b->d_n[p]) HIP_TRY(hipMalloc(&b->d_n[p], sizeof(int)));
+      b->cap_slots[p] = cap;
+      b->dirty = true;  // table addresses changed
+    }
+    if (nt > b->cap_tiles[p]) {
+      b->cap_tiles[p] = std::max(nt, b->cap_tiles[p] + b->cap_tiles[p] / 2);
+      b->dirty = true;
+    }
+    if (b->cap_slots[p] > 0) {
+      b->h_n[p] = ns;
+      if (ns) HIP_TRY(hipMemcpyAsync(b->d_slots[p], b->h_slots[p].data(), ns * sizeof(BatchSlot), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b->d_tile0[p], b->h_tile0[p].data(), (ns + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b->d_n[p], &b->h_n[p], sizeof(int), hipMemcpyHostToDevice, s));
+    }
+  }
+  int rc;
+  if (b->dirty && (rc = batch_capture(b))) return rc;
+  HIP_TRY(hipGraphLaunch(b->exec, s));
+  std::vector<dgm_batch::Slot> still;
+  for (auto& q : b->active) {
+    q.left -= std::min<int64_t>(b->chunk, q.left);
+    if (q.left == 0) {
+      if ((rc = convert<float>(q.m, q.E, 0, false, s))) return rc;
+      if ((rc = convert<float>(q.m, q.H, 1, false, s))) return rc;
+      b->finished.push_back(q.id);
+    } else {
+      still.push_back(q);
+    }
+  }
+  b->active.swap(still);
+  HIP_TRY(hipStreamSynchronize(s));  // host tables are reused by the next advance
+  return DGM_OK;
+}
+
+int dgm_batch_take_finished(dgm_batch* b, int64_t* ids, int64_t cap, int64_t* n) {
+  if (!b || !n || (cap > 0 && !ids)) return fail(DGM_ERR_ARG, "null argument");
+  const int64_t k = std::min<int64_t>(cap, (int64_t)b->finished.size());
+  for (int64_t q = 0; q < k; ++q) ids[q] = b->finished[q];
+  b->finished.erase(b->finished.begin(), b->finished.begin() + k);
+  *n = k;
+  return DGM_OK;
 }
 
 }  // extern "C"

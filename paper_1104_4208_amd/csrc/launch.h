@@ -14,3 +14,25 @@ struct PhaseArgs {
   int blocks;       // ceil(K / 64)
   hipStream_t stream;
 };
+
+// One mesh of a batched launch (FP32 fields in the stored frame).
+struct BatchSlot {
+  const void* E;    // (3,N,K)
+  const void* H;    // (3,N,K)
+  const void* ME;   // (6,K) conversion of E into the derivative frame
+  const void* MH;   // (6,K) conversion of H
+  const int* nbr;   // (4,K)
+  int K;
+  int steps_left;   // sub-steps of the current launch this slot still takes
+  double dt;
+};
+
+struct BatchArgs {
+  const BatchSlot* slots;  // device table, nslots entries
+  const int* tile0;        // device prefix sums of tiles, nslots + 1 entries
+  const int* nslots;       // device scalar
+  int phase;               // 0: H update from E, 1: E update from H
+  int substep;             // index of the leapfrog step inside the launch
+  int blocks;              // grid size (capacity in tiles)
+  hipStream_t stream;
+};

@@ -49,6 +49,12 @@ SIGNATURES = {
     "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
     "dgm_apply_curl_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
+    "dgm_batch_create": (_c_i, [_c_i, ctypes.POINTER(_c_p)]),
+    "dgm_batch_destroy": (_c_i, [_c_p]),
+    "dgm_batch_add": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_d, _c_i64, _c_p, _pi64]),
+    "dgm_batch_num_active": (_c_i, [_c_p, _pi64]),
+    "dgm_batch_advance": (_c_i, [_c_p, _c_p]),
+    "dgm_batch_take_finished": (_c_i, [_c_p, _pi64, _c_i64, _pi64]),
 }
 
 _lib = None
@@ -251,3 +257,54 @@ class Mesh:
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """Slots of independent solves advanced together (dgm_batch_*)."""
+
+    def __init__(self, chunk: int = 20):
+        h = ctypes.c_void_p()
+        _check(load_library().dgm_batch_create(int(chunk), ctypes.byref(h)))
+        self._h = h
+        self.chunk = int(chunk)
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().dgm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, mesh: "Mesh", E, H, dt: float, nsteps: int) -> int:
+        E, H = mesh._field(E, "E"), mesh._field(H, "H")
+        torch = _torch()
+        if E.dtype != torch.float32 or H.dtype != torch.float32:
+            raise DGMError("batched slots take float32 fields")
+        sid = ctypes.c_int64()
+        _check(load_library().dgm_batch_add(self._h, mesh.handle, _ptr(E), _ptr(H), float(dt), int(nsteps),
+                                            _stream(), ctypes.byref(sid)))
+        self._keep[sid.value] = (mesh, E, H)
+        return sid.value
+
+    def num_active(self) -> int:
+        n = ctypes.c_int64()
+        _check(load_library().dgm_batch_num_active(self._h, ctypes.byref(n)))
+        return n.value
+
+    def advance(self):
+        _check(load_library().dgm_batch_advance(self._h, _stream()))
+
+    def take_finished(self):
+        cap = 4096
+        ids = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int64()
+        _check(load_library().dgm_batch_take_finished(self._h, ids, cap, ctypes.byref(n)))
+        out = [ids[i] for i in range(n.value)]
+        for i in out:
+            self._keep.pop(i, None)
+        return out

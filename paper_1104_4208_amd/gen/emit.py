@@ -510,6 +510,27 @@ def _output_job(a_, t, Lp, rows, ind):
     a_(ind + "}")
 
 
+def _phase_body(a_, t, g, Lp, pl, nw):
+    """Stages 1 and 2 of a phase (shared by the single-mesh and the batched kernel)."""
+    a_("  const R m00 = MU[0 * Ks + el], m01 = MU[1 * Ks + el], m02 = MU[2 * Ks + el];")
+    a_("  const R m11 = MU[3 * Ks + el], m12 = MU[4 * Ks + el], m22 = MU[5 * Ks + el];")
+    a_("  // stage 1: jumps of the tangential traces (neighbour minus own) into LDS")
+    for w in range(nw):
+        a_(f"  if (wave == {w}) {{")
+        for (f, rows) in pl["trace"][w]:
+            a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
+            _trace_job(a_, t, g, f, rows, "    ")
+        a_("  }")
+    a_("  __syncthreads();")
+    a_("  // stage 2: curl and lifted jumps, component-separable update")
+    for w in range(nw):
+        a_(f"  if (wave == {w}) {{")
+        for rows in pl["out"][w]:
+            a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
+            _output_job(a_, t, Lp, rows, "    ")
+        a_("  }")
+
+
 def emit_phase(p: int, nw: int = WAVES) -> str:
     t = TB.build(p)
     N, NF = t.N, t.NF
@@ -536,23 +557,39 @@ def emit_phase(p: int, nw: int = WAVES) -> str:
     a_("  const bool act = e < K;")
     a_("  const int el = act ? e : K - 1;")
     a_("  const size_t Ks = (size_t)K;")
-    a_("  const R m00 = MU[0 * Ks + el], m01 = MU[1 * Ks + el], m02 = MU[2 * Ks + el];")
-    a_("  const R m11 = MU[3 * Ks + el], m12 = MU[4 * Ks + el], m22 = MU[5 * Ks + el];")
-    a_("  // stage 1: jumps of the tangential traces (neighbour minus own) into LDS")
-    for w in range(nw):
-        a_(f"  if (wave == {w}) {{")
-        for (f, rows) in pl["trace"][w]:
-            a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ")
-        a_("  }")
-    a_("  __syncthreads();")
-    a_("  // stage 2: curl and lifted jumps, component-separable update")
-    for w in range(nw):
-        a_(f"  if (wave == {w}) {{")
-        for rows in pl["out"][w]:
-            a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
-            _output_job(a_, t, Lp, rows, "    ")
-        a_("  }")
+    _phase_body(a_, t, g, Lp, pl, nw)
+    a_("}")
+    a_("")
+    a_("// Batched variant: one launch advances every slot (mesh) of this order.  Block b")
+    a_("// belongs to the last slot s with tile0[s] <= b; blocks past the table, or of")
+    a_("// slots whose remaining steps are exhausted at this sub-step, exit at once.")
+    a_("template <typename R>")
+    a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
+    a_("    const int* __restrict__ tile0, const int* __restrict__ nslots, int phase, int substep)")
+    a_("{")
+    a_(f"  __shared__ R jmp[{8 * NF * LANES}];")
+    a_("  const int nsl = *nslots;")
+    a_("  const int bid = blockIdx.x;")
+    a_("  if (nsl <= 0 || bid >= tile0[nsl]) return;")
+    a_("  int lo = 0, hi = nsl - 1;")
+    a_("  while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (tile0[mid] <= bid) lo = mid; else hi = mid - 1; }")
+    a_("  const BatchSlot sl = slots[lo];")
+    a_("  if (substep >= sl.steps_left) return;")
+    a_("  const R* __restrict__ U = (const R*)(phase ? sl.H : sl.E);")
+    a_("  R* __restrict__ V = (R*)(phase ? sl.E : sl.H);")
+    a_("  const R* __restrict__ MU = (const R*)(phase ? sl.MH : sl.ME);")
+    a_("  const int* __restrict__ nbr = sl.nbr;")
+    a_("  const R sdt = (R)(phase ? sl.dt : -sl.dt);")
+    a_("  const R wall = phase ? R(1) : R(-1);")
+    a_("  const int K = sl.K;")
+    a_(f"  const int lane = threadIdx.x & {LANES - 1};")
+    a_(f"  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
+    a_("  const int tile = bid - tile0[lo];")
+    a_(f"  const int e = tile * {LANES} + lane;")
+    a_("  const bool act = e < K;")
+    a_("  const int el = act ? e : K - 1;")
+    a_("  const size_t Ks = (size_t)K;")
+    _phase_body(a_, t, g, Lp, pl, nw)
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -584,7 +621,11 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({WAVES * LANES}), 0, a.stream, a.U, a.V, a.MU, a.nbr, a.sdt, a.wall, a.K);",
               "  return hipGetLastError();",
               "}",
-              f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]
+              f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}",
+              f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a) {{",
+              f"  hipLaunchKernelGGL(dgm_phase_batch_p{p}<float>, dim3(a.blocks), dim3({WAVES * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
+              "  return hipGetLastError();",
+              "}"]
         if p <= F64_MAX_ORDER:
             tu.append(f"hipError_t dgm_launch_phase_p{p}_f64(const PhaseArgs<double>& a) {{ return launch_p{p}<double>(a); }}")
         units.append(_write_if_changed(os.path.join(outdir, f"phase_p{p}.hip"), "\n".join(tu) + "\n"))
@@ -603,6 +644,9 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
             decl.append(f"hipError_t dgm_launch_phase_p{p}_f64(const PhaseArgs<double>& a);")
     lines += decl
     lines.append("static hipError_t (*const kPhaseF32[])(const PhaseArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f32" for p in orders) + "};")
+    for p in orders:
+        lines.append(f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a);")
+    lines.append("static hipError_t (*const kBatchF32[])(const BatchArgs&) = {nullptr, " + ", ".join(f"dgm_launch_batch_p{p}_f32" for p in orders) + "};")
     lines.append("static hipError_t (*const kPhaseF64[])(const PhaseArgs<double>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f64" for p in orders if p <= F64_MAX_ORDER) + "};")
     _write_if_changed(os.path.join(outdir, "frame.inc"), "\n".join(lines) + "\n")
     _write_if_changed(os.path.join(outdir, "tables.inc"), emit_host_tables(orders))

@@ -211,3 +211,15 @@ def test_full_size_sampled_apply_curl(n, p):
     ee = rel_err(dE[:, :, centers], ref_de)
     print(f"n={n} p={p} sampled {len(centers)}: dH {eh:.2e} dE {ee:.2e}")
     assert eh < 1e-5 and ee < 1e-5
+
+
+def test_estimate_dt_fp32_path_at_p8():
+    """Above the FP64 orders the power iteration runs on FP32 vectors; both sides
+    approach rho from below, so they agree to within the iteration's convergence."""
+    verts, tets = synth.kuhn_mesh(1)
+    pr = Pair(verts, tets, 8)
+    est_or = pr.s.spectral_radius(150, synth.splitmix64(5, 3 * pr.s.N * 6))
+    m = P.Mesh(verts, tets).set_order(8)
+    dt, est = m.estimate_dt(cfl=0.5, iters=150, seed=5)
+    print(f"p=8 rho: library {est:.6e}, oracle {est_or:.6e}")
+    assert abs(est - est_or) < 1e-2 * est_or

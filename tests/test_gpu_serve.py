@@ -1,0 +1,68 @@
+"""Batched serving: slots of different orders, sizes and step counts advanced
+together give bitwise the same result as each solve alone; a small arrival
+trace completes in both serving modes."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1104_4208_amd as P  # noqa: E402
+from paper_1104_4208_amd import serve  # noqa: E402
+
+
+def _case(n, p, seed):
+    rng = np.random.default_rng(seed)
+    verts, tets = synth.kuhn_mesh(n, 0.1, rng)
+    K, N = tets.shape[0], P.num_modes(p)
+    E = rng.standard_normal((3, N, K)).astype(np.float32)
+    H = rng.standard_normal((3, N, K)).astype(np.float32)
+    eps = rng.choice([1.0, 2.0, 4.0], size=K)
+    return verts, tets, eps, E, H
+
+
+def test_batch_matches_alone_bitwise():
+    cases = [(2, 2, 1, 23), (3, 4, 2, 41), (2, 6, 3, 7), (4, 3, 4, 60), (1, 8, 5, 33), (3, 2, 6, 20)]
+    dt = 2e-3
+    alone, mixed = {}, {}
+    for (n, p, seed, steps) in cases:
+        verts, tets, eps, E, H = _case(n, p, seed)
+        m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
+        Eg, Hg = torch.tensor(E, device="cuda"), torch.tensor(H, device="cuda")
+        m.step(Eg, Hg, dt, steps)
+        torch.cuda.synchronize()
+        alone[seed] = (Eg.cpu().numpy(), Hg.cpu().numpy())
+    b = P.Batch(chunk=16)
+    live = {}
+    for (n, p, seed, steps) in cases:
+        verts, tets, eps, E, H = _case(n, p, seed)
+        m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
+        Eg, Hg = torch.tensor(E, device="cuda"), torch.tensor(H, device="cuda")
+        sid = b.add(m, Eg, Hg, dt, steps)
+        live[sid] = (seed, m, Eg, Hg)
+    rounds = 0
+    while b.num_active():
+        b.advance()
+        rounds += 1
+        for sid in b.take_finished():
+            seed, m, Eg, Hg = live.pop(sid)
+            mixed[seed] = (Eg.cpu().numpy(), Hg.cpu().numpy())
+    assert not live and rounds == 4  # the longest solve takes ceil(60 / 16) launches
+    for seed in alone:
+        assert np.array_equal(alone[seed][0], mixed[seed][0]), seed
+        assert np.array_equal(alone[seed][1], mixed[seed][1]), seed
+
+
+def test_small_trace_both_modes():
+    trace = serve.make_trace(num=10, rate=200.0, n_range=(2, 4), p_range=(2, 5), steps_range=(20, 80))
+    srv = serve.Server(hbm_budget_bytes=4 * 2 ** 20, chunk=8)  # small budget: admission defers
+    ids = set(range(10))
+    rb, sb = srv.run(trace, "batched", keep_states=ids)
+    rs, ss = srv.run(trace, "sequential", keep_states=ids)
+    assert rb["requests"] == rs["requests"] == 10
+    for rid in ids:
+        assert torch.equal(sb[rid][0], ss[rid][0]) and torch.equal(sb[rid][1], ss[rid][1])
+    print(rb, rs)
+    assert rb["p99_latency_s"] >= rb["p50_latency_s"] > 0
