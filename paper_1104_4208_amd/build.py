@@ -27,8 +27,15 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=f
          "-I" + os.path.join(HERE, "..", "include")]
 
 
+def _deps(src):
+    """The source plus the generated kernel body it includes (same stem, .inc)."""
+    inc = src[:-4] + ".inc"
+    return [src, inc] if os.path.exists(inc) else [src]
+
+
 def _compile(src, obj):
-    if os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(src), _newest_header()):
+    newest = max(max(os.path.getmtime(d) for d in _deps(src)), _newest_header())
+    if os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return obj, 0.0, ""
     t0 = time.time()
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj + ".tmp"]
@@ -60,7 +67,7 @@ def build(orders=None, jobs=None, force=False, verbose=True):
                 os.remove(o)
     jobs = jobs or min(8, os.cpu_count() or 4)
     # largest orders first so the long compiles start early
-    order = sorted(range(len(srcs)), key=lambda i: -os.path.getsize(srcs[i]))
+    order = sorted(range(len(srcs)), key=lambda i: -sum(os.path.getsize(d) for d in _deps(srcs[i])))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = {ex.submit(_compile, srcs[i], objs[i]): i for i in order}
         for f in cf.as_completed(futs):

@@ -63,6 +63,7 @@ def _dot(gv, w, name):
 
 WAVES = 4
 LANES = 64
+LDS_BUDGET = 150 * 1024  # bytes of LDS one workgroup may use for the staged field and jumps
 
 
 def _chunks(items, costs, max_cost):
@@ -139,162 +140,6 @@ class _Stream:
                 a_(ind + "  " + st)
             a_(ind + "}")
 
-
-def _chunks(items, costs, max_cost):
-    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
-    out, cur, c = [], [], 0
-    for it, w in zip(items, costs):
-        if cur and c + w > max_cost:
-            out.append(cur)
-            cur, c = [], 0
-        cur.append(it)
-        c += w
-    if cur:
-        out.append(cur)
-    return out
-
-
-def _assign(jobs, costs, nw):
-    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
-    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
-    load = [0] * nw
-    out = [[] for _ in range(nw)]
-    for i in order:
-        w = min(range(nw), key=lambda k: load[k])
-        out[w].append(jobs[i])
-        load[w] += costs[i]
-    return out, load
-
-
-TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
-
-
-def _chunks(items, costs, max_cost):
-    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
-    out, cur, c = [], [], 0
-    for it, w in zip(items, costs):
-        if cur and c + w > max_cost:
-            out.append(cur)
-            cur, c = [], 0
-        cur.append(it)
-        c += w
-    if cur:
-        out.append(cur)
-    return out
-
-
-def _assign(jobs, costs, nw):
-    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
-    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
-    load = [0] * nw
-    out = [[] for _ in range(nw)]
-    for i in order:
-        w = min(range(nw), key=lambda k: load[k])
-        out[w].append(jobs[i])
-        load[w] += costs[i]
-    return out, load
-
-
-TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
-
-
-PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
-
-
-class _Stream:
-    """Emit a stream of mode blocks as separate basic blocks with explicit prefetch.
-
-    Every block sits behind an opaque uniform branch (an offset that is zero but
-    hidden from the compiler by an empty asm statement), so instruction
-    scheduling stays inside one block and register pressure stays bounded; the
-    loads of block b + PREFETCH are issued inside block b into a small ring of
-    registers, which keeps memory latency hidden without hoisting every load of
-    the stream to its start.
-    """
-
-    def __init__(self, a_, ind, tag):
-        self.a_, self.ind, self.tag = a_, ind, tag
-
-    def emit(self, blocks):
-        """blocks: list of (loads, body) with loads = [load expressions, may use o] and
-        body(names) -> list of statements using the loaded values."""
-        a_, ind, tag = self.a_, self.ind, self.tag
-        if not blocks:
-            return
-        nl = max(len(ld) for ld, _ in blocks)
-        slots = [[f"{tag}{r}_{q}" for q in range(nl)] for r in range(PREFETCH)]
-        a_(ind + "R " + ", ".join(f"{v} = R(0)" for r in slots for v in r) + ";")
-        a_(ind + "size_t o = 0;")
-        for bi in range(min(PREFETCH, len(blocks))):
-            for q, expr in enumerate(blocks[bi][0]):
-                a_(ind + f"{slots[bi][q]} = {expr};")
-        for bi, (ld, body) in enumerate(blocks):
-            r = bi % PREFETCH
-            a_(ind + "asm volatile(\"\" : \"+s\"(o));")
-            a_(ind + "if (o == 0) {")
-            names = [f"x{q}" for q in range(len(ld))]
-            for q in range(len(ld)):
-                a_(ind + f"  const R {names[q]} = {slots[r][q]};")
-            nxt = bi + PREFETCH
-            if nxt < len(blocks):
-                for q, expr in enumerate(blocks[nxt][0]):
-                    a_(ind + f"  {slots[r][q]} = {expr};")
-            for st in body(names):
-                a_(ind + "  " + st)
-            a_(ind + "}")
-
-
-def _chunks(items, costs, max_cost):
-    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
-    out, cur, c = [], [], 0
-    for it, w in zip(items, costs):
-        if cur and c + w > max_cost:
-            out.append(cur)
-            cur, c = [], 0
-        cur.append(it)
-        c += w
-    if cur:
-        out.append(cur)
-    return out
-
-
-def _assign(jobs, costs, nw):
-    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
-    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
-    load = [0] * nw
-    out = [[] for _ in range(nw)]
-    for i in order:
-        w = min(range(nw), key=lambda k: load[k])
-        out[w].append(jobs[i])
-        load[w] += costs[i]
-    return out, load
-
-
-TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
-
-
-class _Window:
-    """Software-pipelining window for a stream of mode blocks.
-
-    The compiler would otherwise hoist every load of a straight-line stream to
-    its start (one basic block), holding hundreds of values in registers.  Each
-    block's address offset passes through an empty asm statement that consumes
-    a token produced by the block WINDOW places earlier, so at most WINDOW
-    blocks of loads are in flight and the offset keeps its global address space.
-    """
-
-    def __init__(self, a_, ind, tag):
-        self.a_, self.ind, self.tag, self.n = a_, ind, tag, 0
-        a_(ind + "R " + ", ".join(f"{tag}{i} = R(0)" for i in range(WINDOW)) + ";")
-
-    def begin(self):
-        i = self.n % WINDOW
-        self.a_(self.ind + f"size_t o = 0; asm volatile(\"\" : \"+s\"(o) : \"v\"({self.tag}{i}));")
-        return i
-
-    def end(self, i, value):
-        self.a_(self.ind + f"{self.tag}{i} = {value};")
-        self.n += 1
 
 OUT_ROWS = 16     # volume modes per output job (3 components each)
 CYC = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
@@ -351,17 +196,35 @@ def _hvec(a_, ind, g, f, M, name):
             a_(ind + f"const R {name}{k}{r} = {' + '.join(terms) if terms else 'R(0)'};")
 
 
-def _trace_job(a_, t, g, f, rows, ind):
+def _trace_job(a_, t, g, f, rows, ind, staged=False):
     """Own and neighbour tangential traces of face f on face rows `rows`; the jump
     (neighbour minus own) goes to LDS."""
     N, NF = t.N, t.NF
     a_(ind + "{")
     a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
-    _hvec(a_, ind + "  ", g, f, "m", "h")
+    if not staged:
+        _hvec(a_, ind + "  ", g, f, "m", "h")
     blocks = []
     for a in range(N):
         ms = [m for m in rows if t.T[f][m, a] != 0]
         if not ms:
+            continue
+        if staged:
+            comps = [c for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0]
+
+            def body(x, a=a, ms=ms, comps=comps):
+                xs = dict(zip(comps, x))
+                out = []
+                for k in range(2):
+                    terms = [(g[f][k][c], xs[c]) for c in comps if g[f][k][c] != 0.0]
+                    out.append(f"const R q{k} = " + " + ".join(
+                        (v if c == 1.0 else (f"-{v}" if c == -1.0 else f"{_lit(c)} * {v}")) for c, v in terms) + ";")
+                for m in ms:
+                    for k in range(2):
+                        out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
+                return out
+
+            blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in comps], body))
             continue
 
         def body(x, a=a, ms=ms):
@@ -417,7 +280,7 @@ def _trace_job(a_, t, g, f, rows, ind):
     a_(ind + "}")
 
 
-def _output_job(a_, t, Lp, rows, ind):
+def _output_job(a_, t, Lp, rows, ind, staged=False):
     """All three components of the update on volume rows `rows`: curl in the
     derivative frame (one conversion per streamed mode) plus the lifted jumps."""
     N, NF = t.N, t.NF
@@ -438,7 +301,10 @@ def _output_job(a_, t, Lp, rows, ind):
                 need.add(i)
 
         def body(x, a=a, hits=hits, need=need):
-            out = [f"const R w{c} = {rowsM[c].format(*x)};" for c in sorted(need)]
+            if staged:
+                out = [f"const R w{c} = {v};" for c, v in zip(sorted(need), x)]
+            else:
+                out = [f"const R w{c} = {rowsM[c].format(*x)};" for c in sorted(need)]
             for k in range(3):
                 i, j = CYC[k]
                 for b in hits[i]:
@@ -447,7 +313,10 @@ def _output_job(a_, t, Lp, rows, ind):
                     out.append(_fma(f"acc{k}_{b}", -t.D[j][b, a], f"w{i}"))
             return out
 
-        blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
+        if staged:
+            blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in sorted(need)], body))
+        else:
+            blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
@@ -510,16 +379,42 @@ def _output_job(a_, t, Lp, rows, ind):
     a_(ind + "}")
 
 
-def _phase_body(a_, t, g, Lp, pl, nw):
-    """Stages 1 and 2 of a phase (shared by the single-mesh and the batched kernel)."""
-    a_("  const R m00 = MU[0 * Ks + el], m01 = MU[1 * Ks + el], m02 = MU[2 * Ks + el];")
-    a_("  const R m11 = MU[3 * Ks + el], m12 = MU[4 * Ks + el], m22 = MU[5 * Ks + el];")
+def staged_fits(p: int, elem_bytes: int = 4) -> bool:
+    """Whether a tile's own field (3N x 64) and its jumps (8NF x 64) fit in LDS."""
+    t = TB.build(p)
+    return (3 * t.N + 8 * t.NF) * LANES * elem_bytes <= LDS_BUDGET
+
+
+def waves_for(p: int) -> int:
+    return 8 if p >= 4 else 4
+
+
+def _phase_body(a_, t, g, Lp, pl, nw, staged):
+    """Stages 0-2 of a phase (shared by the single-mesh and the batched kernel)."""
+    N, NF = t.N, t.NF
+    if staged:
+        a_("  // stage 0: the tile's own field in the derivative frame, w = M S, into LDS")
+        a_("  // (each wave converts every nw-th mode of all 64 elements: coalesced loads)")
+        a_("  {")
+        a_("    const R n00 = MU[0 * Ks + el], n01 = MU[1 * Ks + el], n02 = MU[2 * Ks + el];")
+        a_("    const R n11 = MU[3 * Ks + el], n12 = MU[4 * Ks + el], n22 = MU[5 * Ks + el];")
+        a_(f"    for (int a = wave; a < {N}; a += {nw}) {{")
+        a_(f"      const R s0 = U[(size_t)a * Ks + el], s1 = U[(size_t)({N} + a) * Ks + el], s2 = U[(size_t)({2 * N} + a) * Ks + el];")
+        a_(f"      wl[(a) * {LANES} + lane] = n00 * s0 + n01 * s1 + n02 * s2;")
+        a_(f"      wl[({N} + a) * {LANES} + lane] = n01 * s0 + n11 * s1 + n12 * s2;")
+        a_(f"      wl[({2 * N} + a) * {LANES} + lane] = n02 * s0 + n12 * s1 + n22 * s2;")
+        a_("    }")
+        a_("  }")
+        a_("  __syncthreads();")
+    else:
+        a_("  const R m00 = MU[0 * Ks + el], m01 = MU[1 * Ks + el], m02 = MU[2 * Ks + el];")
+        a_("  const R m11 = MU[3 * Ks + el], m12 = MU[4 * Ks + el], m22 = MU[5 * Ks + el];")
     a_("  // stage 1: jumps of the tangential traces (neighbour minus own) into LDS")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for (f, rows) in pl["trace"][w]:
             a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ")
+            _trace_job(a_, t, g, f, rows, "    ", staged)
         a_("  }")
     a_("  __syncthreads();")
     a_("  // stage 2: curl and lifted jumps, component-separable update")
@@ -527,25 +422,39 @@ def _phase_body(a_, t, g, Lp, pl, nw):
         a_(f"  if (wave == {w}) {{")
         for rows in pl["out"][w]:
             a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
-            _output_job(a_, t, Lp, rows, "    ")
+            _output_job(a_, t, Lp, rows, "    ", staged)
         a_("  }")
 
 
-def emit_phase(p: int, nw: int = WAVES) -> str:
+def _kernel_setup(p):
     t = TB.build(p)
-    N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
-    pl = plan(p, nw)
+    nw = waves_for(p)
+    staged = staged_fits(p, 4) and (p > F64_MAX_ORDER or staged_fits(p, 8))
+    return t, g, Lp, nw, staged, plan(p, nw)
+
+
+def _lds_decl(a_, t, staged):
+    a_(f"  __shared__ R jmp[{8 * t.NF * LANES}];")
+    if staged:
+        a_(f"  __shared__ R wl[{3 * t.N * LANES}];")
+
+
+def emit_phase(p: int) -> str:
+    """Single-mesh phase kernel of order p."""
+    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    N, NF = t.N, t.NF
     L = []
     a_ = L.append
     a_(f"// Generated by gen/emit.py for order p = {p}: N = {N} volume modes, NF = {NF} face modes.")
-    a_(f"// {nw} waves share {LANES} elements (one per lane); trace cost per wave {pl['trace_load']},")
-    a_(f"// output cost per wave {pl['out_load']}.")
+    a_(f"// {nw} waves share {LANES} elements (one per lane); own field staged in LDS: {staged};")
+    a_(f"// trace cost per wave {pl['trace_load']}, output cost per wave {pl['out_load']}.")
+    a_(f"static constexpr int kWaves_p{p} = {nw};")
     a_("template <typename R>")
     a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const int* __restrict__ nbr, R sdt, R wall, int K)")
     a_("{")
-    a_(f"  __shared__ R jmp[{8 * NF * LANES}];")
+    _lds_decl(a_, t, staged)
     a_(f"  const int lane = threadIdx.x & {LANES - 1};")
     a_(f"  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
     a_("  // XCD-aware tile order: block b runs on XCD b % 8, so give every XCD a")
@@ -557,17 +466,27 @@ def emit_phase(p: int, nw: int = WAVES) -> str:
     a_("  const bool act = e < K;")
     a_("  const int el = act ? e : K - 1;")
     a_("  const size_t Ks = (size_t)K;")
-    _phase_body(a_, t, g, Lp, pl, nw)
+    _phase_body(a_, t, g, Lp, pl, nw, staged)
     a_("}")
-    a_("")
-    a_("// Batched variant: one launch advances every slot (mesh) of this order.  Block b")
-    a_("// belongs to the last slot s with tile0[s] <= b; blocks past the table, or of")
-    a_("// slots whose remaining steps are exhausted at this sub-step, exit at once.")
+    return "\n".join(L) + "\n"
+
+
+def emit_batch(p: int) -> str:
+    """Batched multi-mesh phase kernel of order p (FP32)."""
+    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    N, NF = t.N, t.NF
+    L = []
+    a_ = L.append
+    a_(f"// Generated by gen/emit.py for order p = {p}: batched variant, {nw} waves per 64 elements.")
+    a_("// One launch advances every slot (mesh) of this order.  Block b belongs to the last")
+    a_("// slot s with tile0[s] <= b; blocks past the table, or of slots whose remaining")
+    a_("// steps are exhausted at this sub-step, exit before any barrier.")
+    a_(f"static constexpr int kBatchWaves_p{p} = {nw};")
     a_("template <typename R>")
     a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
     a_("    const int* __restrict__ tile0, const int* __restrict__ nslots, int phase, int substep)")
     a_("{")
-    a_(f"  __shared__ R jmp[{8 * NF * LANES}];")
+    _lds_decl(a_, t, staged)
     a_("  const int nsl = *nslots;")
     a_("  const int bid = blockIdx.x;")
     a_("  if (nsl <= 0 || bid >= tile0[nsl]) return;")
@@ -589,12 +508,12 @@ def emit_phase(p: int, nw: int = WAVES) -> str:
     a_("  const bool act = e < K;")
     a_("  const int el = act ? e : K - 1;")
     a_("  const size_t Ks = (size_t)K;")
-    _phase_body(a_, t, g, Lp, pl, nw)
+    _phase_body(a_, t, g, Lp, pl, nw, staged)
     a_("}")
     return "\n".join(L) + "\n"
 
 
-F64_MAX_ORDER = 6
+F64_MAX_ORDER = 4
 
 
 def _write_if_changed(path, src):
@@ -611,24 +530,31 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     os.makedirs(outdir, exist_ok=True)
     units = []
     for p in orders:
+        nw = waves_for(p)
         _write_if_changed(os.path.join(outdir, f"phase_p{p}.inc"), emit_phase(p))
+        _write_if_changed(os.path.join(outdir, f"batch_p{p}.inc"), emit_batch(p))
         tu = [f"// Generated by gen/emit.py: instantiation and launcher for order {p}.",
               "#include <hip/hip_runtime.h>",
               '#include "../launch.h"',
               f'#include "phase_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_p{p}(const PhaseArgs<R>& a) {{",
-              f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({WAVES * LANES}), 0, a.stream, a.U, a.V, a.MU, a.nbr, a.sdt, a.wall, a.K);",
+              f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.nbr, a.sdt, a.wall, a.K);",
               "  return hipGetLastError();",
               "}",
-              f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}",
-              f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a) {{",
-              f"  hipLaunchKernelGGL(dgm_phase_batch_p{p}<float>, dim3(a.blocks), dim3({WAVES * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
-              "  return hipGetLastError();",
-              "}"]
+              f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]
         if p <= F64_MAX_ORDER:
             tu.append(f"hipError_t dgm_launch_phase_p{p}_f64(const PhaseArgs<double>& a) {{ return launch_p{p}<double>(a); }}")
         units.append(_write_if_changed(os.path.join(outdir, f"phase_p{p}.hip"), "\n".join(tu) + "\n"))
+        tb = [f"// Generated by gen/emit.py: batched launcher for order {p}.",
+              "#include <hip/hip_runtime.h>",
+              '#include "../launch.h"',
+              f'#include "batch_p{p}.inc"',
+              f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a) {{",
+              f"  hipLaunchKernelGGL(dgm_phase_batch_p{p}<float>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
+              "  return hipGetLastError();",
+              "}"]
+        units.append(_write_if_changed(os.path.join(outdir, f"batch_p{p}.hip"), "\n".join(tb) + "\n"))
     fr = TB.frame()
     A, Ai = fr["A"], fr["Ainv"]
     lines = ["// Generated by gen/emit.py: derivative frame and compiled orders.",

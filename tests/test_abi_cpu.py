@@ -42,7 +42,7 @@ def test_mode_counts_and_order():
         assert all(0 <= min(m) and sum(m) <= p for m in tab)
     with pytest.raises(P.DGMError):
         P.mode_index(2, 10)
-    assert P.max_order(P.DGM_F32) >= 8 and P.max_order(P.DGM_F64) >= 6
+    assert P.max_order(P.DGM_F32) >= 8 and P.max_order(P.DGM_F64) >= 4
 
 
 def _create(verts, tets):
