@@ -107,7 +107,11 @@ int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void
 
 /* nsteps symplectic Euler steps in place (Section 3):
  *     H <- H + dt M_mu^{-1} C E,   E <- E - dt M_eps^{-1} C^T H.
- * dt is the caller's (see dgm_estimate_dt); nsteps >= 0. */
+ * dt is the caller's (see dgm_estimate_dt); nsteps >= 0.  Each half step is one
+ * kernel that also writes the tangential face traces of the field it updated
+ * (element-major, 2 (p+1)(p+2) values per face rounded up to a multiple of 4)
+ * for the neighbours in the next half step; the handle keeps these two buffers
+ * (allocated on first use, 2 K x 4 x that stride values of dtype). */
 int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
 
 /* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),
@@ -151,7 +155,8 @@ int dgm_step_dense(dgm_mesh* mesh, int prec, float* E, float* H, double dt, int6
  * layout and reported by dgm_batch_take_finished.  Between dgm_batch_add and
  * completion, E and H hold the library's internal stored-frame coefficients
  * and must not be read or written by the caller.  A mesh handle may back at
- * most one active slot.  Results are bitwise equal to dgm_step on the same
+ * most one active slot and must not be passed to other calls while its slot is
+ * active (the slot runs on the handle's trace buffers).  Results are bitwise equal to dgm_step on the same
  * slot alone (same kernels, same per-element arithmetic).  Not part of the
  * paper (its solver runs one mesh on one core); this is the serving layer. */
 typedef struct dgm_batch dgm_batch;

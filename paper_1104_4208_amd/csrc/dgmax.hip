@@ -45,6 +45,7 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 int num_modes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+int num_face_modes(int p) { return (p + 1) * (p + 2) / 2; }
 
 // ---------------------------------------------------------------- kernels
 // X_m <- P X_m for every mode m of every element, P = (Minv A) (to the stored
@@ -176,6 +177,8 @@ struct dgm_mesh {
   double* d_G[2] = {nullptr, nullptr};       // |J| eps F^-1 F^-T (energy)
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  void* d_T = nullptr;      // element-major traces of E then H (K x ES each)
+  size_t T_bytes = 0;
   double* d_partial = nullptr;
   int partial_n = 0;
   // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
@@ -193,6 +196,23 @@ int ensure_scratch(dgm_mesh* m, size_t bytes) {
   m->scratch_bytes = 0;
   HIP_TRY(hipMalloc(&m->d_scratch, bytes));
   m->scratch_bytes = bytes;
+  return DGM_OK;
+}
+
+// Trace buffers of both fields (E, then H) in precision R, grown on demand.
+template <typename R>
+int ensure_traces(dgm_mesh* m, R** TE, R** TH) {
+  const size_t per = (size_t)m->K * trace_elem_stride(num_face_modes(m->p));
+  const size_t bytes = 2 * per * sizeof(R);
+  if (m->T_bytes < bytes) {
+    if (m->d_T) HIP_TRY(hipFree(m->d_T));
+    m->d_T = nullptr;
+    m->T_bytes = 0;
+    HIP_TRY(hipMalloc(&m->d_T, bytes));
+    m->T_bytes = bytes;
+  }
+  *TE = static_cast<R*>(m->d_T);
+  *TH = *TE + per;
   return DGM_OK;
 }
 
@@ -297,6 +317,8 @@ template <> double* Minvdev<double>(dgm_mesh* m, int fld) { return m->d_Minv64[f
 
 hipError_t phase(const PhaseArgs<float>& a, int p) { return kPhaseF32[p](a); }
 hipError_t phase(const PhaseArgs<double>& a, int p) { return kPhaseF64[p](a); }
+hipError_t trace(const TraceArgs<float>& a, int p) { return kTraceF32[p](a); }
+hipError_t trace(const TraceArgs<double>& a, int p) { return kTraceF64[p](a); }
 
 int check_order(dgm_mesh* m, int dtype) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
@@ -329,14 +351,32 @@ int fill(R* X, size_t n, R v, hipStream_t s) {
   return DGM_OK;
 }
 
-// One phase on stored-frame data.  fld_u: 0 if U is E (H update), 1 if U is H.
+// Element-major traces T of the stored-frame field U (fld 0: E, 1: H).
 template <typename R>
-int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, hipStream_t s) {
+int run_trace(dgm_mesh* m, const R* U, int fld, R* T, hipStream_t s) {
+  TraceArgs<R> a;
+  a.U = U;
+  a.MU = Mdev<R>(m, fld);
+  a.T = T;
+  a.K = (int)m->K;
+  a.blocks = (int)((m->K + 63) / 64);
+  a.stream = s;
+  HIP_TRY(trace(a, m->p));
+  return DGM_OK;
+}
+
+// One phase on stored-frame data.  fld_u: 0 if U is E (H update), 1 if U is H.
+// Tin holds the traces of U; Tout (or nullptr) receives those of the updated V.
+template <typename R>
+int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin, R* Tout, hipStream_t s) {
   PhaseArgs<R> a;
   a.U = U;
   a.V = V;
   a.MU = Mdev<R>(m, fld_u);
+  a.MV = Mdev<R>(m, 1 - fld_u);
   a.nbr = m->d_nbr;
+  a.Tin = Tin;
+  a.Tout = Tout;
   a.sdt = (R)sdt;
   a.wall = fld_u == 0 ? (R)-1 : (R)1;
   a.K = (int)m->K;
@@ -354,10 +394,13 @@ int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s) {
   int rc;
   if ((rc = ensure_scratch(m, n * sizeof(R)))) return rc;
   R* tmp = static_cast<R*>(m->d_scratch);
+  R* T[2];
+  if ((rc = ensure_traces<R>(m, &T[0], &T[1]))) return rc;
   HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(R), hipMemcpyDeviceToDevice, s));
   if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
+  if ((rc = run_trace<R>(m, tmp, fld_u, T[fld_u], s))) return rc;
   if ((rc = fill<R>(out, n, (R)0, s))) return rc;
-  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, s))) return rc;
+  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s))) return rc;
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
 
@@ -365,11 +408,16 @@ template <typename R>
 int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s) {
   int rc;
   if (nsteps == 0) return DGM_OK;
+  R *TE, *TH;
+  if ((rc = ensure_traces<R>(m, &TE, &TH))) return rc;
   if ((rc = convert<R>(m, E, 0, true, s))) return rc;
   if ((rc = convert<R>(m, H, 1, true, s))) return rc;
+  if ((rc = run_trace<R>(m, E, 0, TE, s))) return rc;
   for (int64_t it = 0; it < nsteps; ++it) {
-    if ((rc = run_phase<R>(m, E, H, 0, -dt, s))) return rc;  // H update from curl E
-    if ((rc = run_phase<R>(m, H, E, 1, dt, s))) return rc;   // E update from curl H
+    // H update from curl E (writes the traces of H), then E update from curl H
+    // (writes the traces of E for the next step, except after the last one)
+    if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s))) return rc;
+    if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s))) return rc;
   }
   if ((rc = convert<R>(m, E, 0, false, s))) return rc;
   return convert<R>(m, H, 1, false, s);
@@ -638,6 +686,7 @@ int dgm_destroy(dgm_mesh* m) {
     hipFree(m->d_G[f]);
   }
   hipFree(m->d_scratch);
+  hipFree(m->d_T);
   hipFree(m->d_partial);
   dense_free(m->dense[0]);
   dense_free(m->dense[1]);
@@ -849,8 +898,11 @@ int dgm_batch_add(dgm_batch* b, dgm_mesh* m, float* E, float* H, double dt, int6
   if (rc) return rc;
   for (const auto& q : b->active)
     if (q.m == m) return fail(DGM_ERR_ARG, "mesh handle already has an active slot");
+  float *TE, *TH;
+  if ((rc = ensure_traces<float>(m, &TE, &TH))) return rc;
   if ((rc = convert<float>(m, E, 0, true, s))) return rc;
   if ((rc = convert<float>(m, H, 1, true, s))) return rc;
+  if ((rc = run_trace<float>(m, E, 0, TE, s))) return rc;
   *id = b->next_id++;
   if (nsteps == 0) {
     if ((rc = convert<float>(m, E, 0, false, s))) return rc;
@@ -883,6 +935,8 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
     bs.ME = q.m->d_M32[0];
     bs.MH = q.m->d_M32[1];
     bs.nbr = q.m->d_nbr;
+    bs.TE = q.m->d_T;
+    bs.TH = static_cast<const float*>(q.m->d_T) + (size_t)q.m->K * trace_elem_stride(num_face_modes(p));
     bs.K = (int)q.m->K;
     bs.steps_left = (int)std::min<int64_t>(b->chunk, q.left);
     bs.dt = q.dt;

@@ -64,6 +64,7 @@ def _dot(gv, w, name):
 WAVES = 4
 LANES = 64
 LDS_BUDGET = 150 * 1024  # bytes of LDS one workgroup may use for the staged field and jumps
+F64_MAX_ORDER = 4   # highest order also instantiated in FP64 (compile time grows steeply with p)
 
 
 def _chunks(items, costs, max_cost):
@@ -154,7 +155,7 @@ def _lift_per_scalar(t, f, rows, Lp):
 
 
 def plan(p: int, nw: int = WAVES):
-    """Split one phase into trace jobs (face f, face rows: own + neighbour traces) and
+    """Split one phase into trace jobs (face f, face rows: own traces) and
     output jobs (volume rows, all three components), balanced over nw waves."""
     t = TB.build(p)
     N, NF = t.N, t.NF
@@ -164,10 +165,8 @@ def plan(p: int, nw: int = WAVES):
         for r0 in range(0, NF, TRACE_ROWS):
             rows = list(range(r0, min(NF, r0 + TRACE_ROWS)))
             own = 2 * np.count_nonzero(t.T[f][rows]) + 6 * np.count_nonzero(np.any(t.T[f][rows] != 0, axis=0))
-            nb = max(2 * np.count_nonzero(t.T[h][rows]) + 6 * np.count_nonzero(np.any(t.T[h][rows] != 0, axis=0))
-                     for h in range(4))
             tr_items.append((f, rows))
-            tr_cost.append(int(own + nb))
+            tr_cost.append(int(own))
     rc = []
     for b in range(N):
         c = sum(np.count_nonzero(t.D[d][b]) for d in range(3)) * 2 // 3 * 3 // 2
@@ -196,14 +195,31 @@ def _hvec(a_, ind, g, f, M, name):
             a_(ind + f"const R {name}{k}{r} = {' + '.join(terms) if terms else 'R(0)'};")
 
 
-def _trace_job(a_, t, g, f, rows, ind, staged=False):
-    """Own and neighbour tangential traces of face f on face rows `rows`; the jump
-    (neighbour minus own) goes to LDS."""
+def trace_strides(NF: int):
+    """Element-major trace buffer: per element four faces of FS values (2 NF traces,
+    tangent k major, padded to a multiple of four), element stride ES = 4 FS."""
+    FS = (2 * NF + 3) & ~3
+    return FS, 4 * FS
+
+
+def _trace_job(a_, t, g, f, rows, ind, src, sink):
+    """Tangential traces tau_k = g_fk . w of one field on face f, face rows `rows`.
+
+    src "lds": the field is staged in LDS (wl) in the derivative frame.
+    src (ptr, mprefix): the field is read from global memory in the stored frame and
+    converted on the fly with h_k = M g_fk (M held in registers mprefix00..22).
+    sink "jump": stage 1 of a phase; the neighbour traces already in jmp become the
+    jump (neighbour minus own), on walls (wall - 1) times the own trace.
+    sink "store": the traces go to the element-major staging area (row stride ES + 1)
+    that is copied out to the trace buffer."""
     N, NF = t.N, t.NF
+    FS, ES = trace_strides(NF)
     a_(ind + "{")
     a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
+    staged = src == "lds"
     if not staged:
-        _hvec(a_, ind + "  ", g, f, "m", "h")
+        ptr, mp = src
+        _hvec(a_, ind + "  ", g, f, mp, "h")
     blocks = []
     for a in range(N):
         ms = [m for m in rows if t.T[f][m, a] != 0]
@@ -234,49 +250,21 @@ def _trace_job(a_, t, g, f, rows, ind, staged=False):
                     out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
             return out
 
-        blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
+        blocks.append(([f"{ptr}[o + ({a}) * Ks + el]", f"{ptr}[o + ({N + a}) * Ks + el]",
+                        f"{ptr}[o + ({2 * N + a}) * Ks + el]"], body))
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
-    a_(ind + f"  const int code = nbr[{f} * Ks + el];")
-    a_(ind + "  if (code < 0) {")
-    for m in rows:
-        for k in range(2):
-            a_(ind + f"    ts{k}_{m} = (wall - R(1)) * ts{k}_{m};")
-    a_(ind + "  } else {")
-    a_(ind + "    const size_t nb = (size_t)(code >> 2);")
-    a_(ind + "    const R n00 = MU[0 * Ks + nb], n01 = MU[1 * Ks + nb], n02 = MU[2 * Ks + nb];")
-    a_(ind + "    const R n11 = MU[3 * Ks + nb], n12 = MU[4 * Ks + nb], n22 = MU[5 * Ks + nb];")
-    a_(ind + "    R " + ", ".join(f"tn{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
-    a_(ind + "    switch (code & 3) {")
-    for gf in range(4):
-        a_(ind + f"    case {gf}: {{")
-        _hvec(a_, ind + "      ", g, gf, "n", "z")
-        blocks = []
-        for a in range(N):
-            ms = [m for m in rows if t.T[gf][m, a] != 0]
-            if not ms:
-                continue
-
-            def body(x, a=a, ms=ms, gf=gf):
-                out = [f"const R q0 = z00 * {x[0]} + z01 * {x[1]} + z02 * {x[2]}, q1 = z10 * {x[0]} + z11 * {x[1]} + z12 * {x[2]};"]
-                for m in ms:
-                    for k in range(2):
-                        out.append(_fma(f"tn{k}_{m}", t.T[gf][m, a], f"q{k}"))
-                return out
-
-            blocks.append(([f"U[o + ({a}) * Ks + nb]", f"U[o + ({N + a}) * Ks + nb]", f"U[o + ({2 * N + a}) * Ks + nb]"], body))
-        _Stream(a_, ind + "      ", "pn").emit(blocks)
-        a_(ind + "      break;")
-        a_(ind + "    }")
-    a_(ind + "    }")
-    for m in rows:
-        for k in range(2):
-            a_(ind + f"    ts{k}_{m} = tn{k}_{m} - ts{k}_{m};")
-    a_(ind + "  }")
-    for m in rows:
-        for k in range(2):
-            a_(ind + f"  jmp[({(f * 2 + k) * NF + m}) * {LANES} + lane] = ts{k}_{m};")
+    if sink == "jump":
+        a_(ind + f"  const int code = nbr[{f} * Ks + el];")
+        a_(ind + "  const R cw = code < 0 ? wall - R(1) : R(-1);")
+        for m in rows:
+            for k in range(2):
+                a_(ind + f"  jmp[({(f * 2 + k) * NF + m}) * {LANES} + lane] += cw * ts{k}_{m};")
+    else:
+        for m in rows:
+            for k in range(2):
+                a_(ind + f"  jmp[lane * {ES + 1} + {f * FS + k * NF + m}] = ts{k}_{m};")
     a_(ind + "}")
 
 
@@ -379,42 +367,109 @@ def _output_job(a_, t, Lp, rows, ind, staged=False):
     a_(ind + "}")
 
 
+def _lds_floats(t, staged):
+    """LDS words of one workgroup: the staged field (3N x 64) and the area shared by
+    the jumps (8NF x 64) and the element-major trace staging (64 x (ES + 1))."""
+    _, ES = trace_strides(t.NF)
+    jm = max(8 * t.NF * LANES, LANES * (ES + 1))
+    return (3 * t.N * LANES if staged else 0) + jm, jm
+
+
 def staged_fits(p: int, elem_bytes: int = 4) -> bool:
-    """Whether a tile's own field (3N x 64) and its jumps (8NF x 64) fit in LDS."""
-    t = TB.build(p)
-    return (3 * t.N + 8 * t.NF) * LANES * elem_bytes <= LDS_BUDGET
+    """Whether a tile's own field and the jump/trace area fit in the LDS budget."""
+    return _lds_floats(TB.build(p), True)[0] * elem_bytes <= LDS_BUDGET
 
 
 def waves_for(p: int) -> int:
     return 8 if p >= 4 else 4
 
 
-def _phase_body(a_, t, g, Lp, pl, nw, staged):
-    """Stages 0-2 of a phase (shared by the single-mesh and the batched kernel)."""
-    N, NF = t.N, t.NF
-    if staged:
-        a_("  // stage 0: the tile's own field in the derivative frame, w = M S, into LDS")
-        a_("  // (each wave converts every nw-th mode of all 64 elements: coalesced loads)")
-        a_("  {")
-        a_("    const R n00 = MU[0 * Ks + el], n01 = MU[1 * Ks + el], n02 = MU[2 * Ks + el];")
-        a_("    const R n11 = MU[3 * Ks + el], n12 = MU[4 * Ks + el], n22 = MU[5 * Ks + el];")
-        a_(f"    for (int a = wave; a < {N}; a += {nw}) {{")
-        a_(f"      const R s0 = U[(size_t)a * Ks + el], s1 = U[(size_t)({N} + a) * Ks + el], s2 = U[(size_t)({2 * N} + a) * Ks + el];")
-        a_(f"      wl[(a) * {LANES} + lane] = n00 * s0 + n01 * s1 + n02 * s2;")
-        a_(f"      wl[({N} + a) * {LANES} + lane] = n01 * s0 + n11 * s1 + n12 * s2;")
-        a_(f"      wl[({2 * N} + a) * {LANES} + lane] = n02 * s0 + n12 * s1 + n22 * s2;")
-        a_("    }")
-        a_("  }")
-        a_("  __syncthreads();")
-    else:
-        a_("  const R m00 = MU[0 * Ks + el], m01 = MU[1 * Ks + el], m02 = MU[2 * Ks + el];")
-        a_("  const R m11 = MU[3 * Ks + el], m12 = MU[4 * Ks + el], m22 = MU[5 * Ks + el];")
-    a_("  // stage 1: jumps of the tangential traces (neighbour minus own) into LDS")
+def _stage_field(a_, t, nw, X, mp):
+    """wl = M X for the tile (M from the 6-component table mp): each wave converts
+    every nw-th mode of all 64 elements with coalesced loads."""
+    N = t.N
+    a_("  {")
+    a_(f"    const R n00 = {mp}[0 * Ks + el], n01 = {mp}[1 * Ks + el], n02 = {mp}[2 * Ks + el];")
+    a_(f"    const R n11 = {mp}[3 * Ks + el], n12 = {mp}[4 * Ks + el], n22 = {mp}[5 * Ks + el];")
+    a_(f"    for (int a = wave; a < {N}; a += {nw}) {{")
+    a_(f"      const R s0 = {X}[(size_t)a * Ks + el], s1 = {X}[(size_t)({N} + a) * Ks + el], s2 = {X}[(size_t)({2 * N} + a) * Ks + el];")
+    a_(f"      wl[(a) * {LANES} + lane] = n00 * s0 + n01 * s1 + n02 * s2;")
+    a_(f"      wl[({N} + a) * {LANES} + lane] = n01 * s0 + n11 * s1 + n12 * s2;")
+    a_(f"      wl[({2 * N} + a) * {LANES} + lane] = n02 * s0 + n12 * s1 + n22 * s2;")
+    a_("    }")
+    a_("  }")
+
+
+def _load_m(a_, mp, reg):
+    a_(f"  const R {reg}00 = {mp}[0 * Ks + el], {reg}01 = {mp}[1 * Ks + el], {reg}02 = {mp}[2 * Ks + el];")
+    a_(f"  const R {reg}11 = {mp}[3 * Ks + el], {reg}12 = {mp}[4 * Ks + el], {reg}22 = {mp}[5 * Ks + el];")
+
+
+def _neighbour_pass(a_, t, nw):
+    """jmp <- neighbour traces (0 on walls): per face 2 NF contiguous values of the
+    neighbour's face block, four per 16-byte load."""
+    NF = t.NF
+    FS, ES = trace_strides(NF)
+    FQ = FS // 4
+    a_("  // neighbour traces from the other field's trace buffer (0 on walls)")
+    a_(f"  for (int q = wave; q < {4 * FQ}; q += {nw}) {{")
+    a_(f"    const int f = q / {FQ}, c = 4 * (q - f * {FQ});")
+    a_("    const int code = nbr[f * Ks + el];")
+    a_("    R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);")
+    a_("    if (code >= 0) {")
+    a_(f"      const R* s = (const R*)__builtin_assume_aligned(Tin + (size_t)(code >> 2) * {ES} + (code & 3) * {FS} + c, 16);")
+    a_("      v0 = s[0]; v1 = s[1]; v2 = s[2]; v3 = s[3];")
+    a_("    }")
+    a_(f"    R* d = jmp + (f * {2 * NF} + c) * {LANES} + lane;")
+    a_(f"    d[0] = v0;")
+    a_(f"    if (c + 1 < {2 * NF}) d[{LANES}] = v1;")
+    a_(f"    if (c + 2 < {2 * NF}) d[{2 * LANES}] = v2;")
+    a_(f"    if (c + 3 < {2 * NF}) d[{3 * LANES}] = v3;")
+    a_("  }")
+
+
+def _trace_stage(a_, t, g, pl, nw, src):
+    """Own traces of one field into the staging area, then one coalesced copy of the
+    tile's contiguous block (64 elements x ES values) to the trace buffer."""
+    NF = t.NF
+    FS, ES = trace_strides(NF)
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for (f, rows) in pl["trace"][w]:
             a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ", staged)
+            _trace_job(a_, t, g, f, rows, "    ", src, "store")
+        a_("  }")
+    a_("  __syncthreads();")
+    a_("  {")
+    a_(f"    const int nel = K - tile * {LANES} < {LANES} ? K - tile * {LANES} : {LANES};")
+    a_(f"    R* __restrict__ dst = Tout + (size_t)tile * {LANES * ES};")
+    a_(f"    for (int i = threadIdx.x; i < nel * {ES}; i += {nw * LANES}) {{")
+    a_(f"      const int q = i / {ES}, c = i - q * {ES};")
+    a_(f"      dst[i] = (c % {FS}) < {2 * NF} ? jmp[q * {ES + 1} + c] : R(0);")
+    a_("    }")
+    a_("  }")
+
+
+def _phase_body(a_, t, g, Lp, pl, nw, staged):
+    """Stages of one phase (shared by the single-mesh and the batched kernel):
+    0 stage U (derivative frame) and gather the neighbour traces, 1 own traces ->
+    jumps, 2 curl + lift + update of V, 3 (if Tout) traces of the new V."""
+    N, NF = t.N, t.NF
+    if staged:
+        a_("  // stage 0: the tile's own field in the derivative frame, w = M S, into LDS")
+        _stage_field(a_, t, nw, "U", "MU")
+        src = "lds"
+    else:
+        _load_m(a_, "MU", "m")
+        src = ("U", "m")
+    _neighbour_pass(a_, t, nw)
+    a_("  __syncthreads();")
+    a_("  // stage 1: jumps of the tangential traces (neighbour minus own) in LDS")
+    for w in range(nw):
+        a_(f"  if (wave == {w}) {{")
+        for (f, rows) in pl["trace"][w]:
+            a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
+            _trace_job(a_, t, g, f, rows, "    ", src, "jump")
         a_("  }")
     a_("  __syncthreads();")
     a_("  // stage 2: curl and lifted jumps, component-separable update")
@@ -424,6 +479,16 @@ def _phase_body(a_, t, g, Lp, pl, nw, staged):
             a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
             _output_job(a_, t, Lp, rows, "    ", staged)
         a_("  }")
+    a_("  if (Tout == nullptr) return;")
+    a_("  // stage 3: traces of the updated field for the next phase (V re-read from L2)")
+    a_("  __syncthreads();")
+    if staged:
+        _stage_field(a_, t, nw, "V", "MV")
+        a_("  __syncthreads();")
+        _trace_stage(a_, t, g, pl, nw, "lds")
+    else:
+        _load_m(a_, "MV", "mv")
+        _trace_stage(a_, t, g, pl, nw, ("V", "mv"))
 
 
 def _kernel_setup(p):
@@ -435,38 +500,78 @@ def _kernel_setup(p):
 
 
 def _lds_decl(a_, t, staged):
-    a_(f"  __shared__ R jmp[{8 * t.NF * LANES}];")
+    tot, jm = _lds_floats(t, staged)
+    a_(f"  __shared__ R jmp[{jm}];")
     if staged:
         a_(f"  __shared__ R wl[{3 * t.N * LANES}];")
+
+
+def _tile_prologue(a_):
+    a_("  const int nbk = gridDim.x, bid = blockIdx.x;")
+    a_("  // XCD-aware tile order: block b runs on XCD b % 8, so give every XCD a")
+    a_("  // contiguous range of element tiles and keep neighbour data in its L2")
+    a_("  const int per = nbk >> 3, rem = nbk & 7, xcd = bid & 7;")
+    a_("  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);")
+
+
+def _elem_prologue(a_):
+    a_(f"  const int lane = threadIdx.x & {LANES - 1};")
+    a_("  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
+    a_(f"  const int e = tile * {LANES} + lane;")
+    a_("  const bool act = e < K;")
+    a_("  const int el = act ? e : K - 1;")
+    a_("  const size_t Ks = (size_t)K;")
+
+
+def _header(a_, p, t, nw, staged, pl, what):
+    FS, ES = trace_strides(t.NF)
+    a_(f"// Generated by gen/emit.py for order p = {p}: N = {t.N} volume modes, NF = {t.NF} face modes; {what}.")
+    a_(f"// {nw} waves share {LANES} elements (one per lane); own field staged in LDS: {staged};")
+    a_(f"// trace buffer strides: face {FS}, element {ES}; trace cost per wave {pl['trace_load']},")
+    a_(f"// output cost per wave {pl['out_load']}.")
+    a_(f"static_assert(trace_face_stride({t.NF}) == {FS} && trace_elem_stride({t.NF}) == {ES}, \"trace layout\");")
 
 
 def emit_phase(p: int) -> str:
     """Single-mesh phase kernel of order p."""
     t, g, Lp, nw, staged, pl = _kernel_setup(p)
-    N, NF = t.N, t.NF
     L = []
     a_ = L.append
-    a_(f"// Generated by gen/emit.py for order p = {p}: N = {N} volume modes, NF = {NF} face modes.")
-    a_(f"// {nw} waves share {LANES} elements (one per lane); own field staged in LDS: {staged};")
-    a_(f"// trace cost per wave {pl['trace_load']}, output cost per wave {pl['out_load']}.")
-    a_(f"static constexpr int kWaves_p{p} = {nw};")
+    _header(a_, p, t, nw, staged, pl, "single-mesh phase")
     a_("template <typename R>")
     a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
-    a_("    const R* __restrict__ MU, const int* __restrict__ nbr, R sdt, R wall, int K)")
+    a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
+    a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K)")
     a_("{")
     _lds_decl(a_, t, staged)
-    a_(f"  const int lane = threadIdx.x & {LANES - 1};")
-    a_(f"  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
-    a_("  // XCD-aware tile order: block b runs on XCD b % 8, so give every XCD a")
-    a_("  // contiguous range of element tiles and keep neighbour data in its L2")
-    a_("  const int nbk = gridDim.x, bid = blockIdx.x;")
-    a_("  const int per = nbk >> 3, rem = nbk & 7, xcd = bid & 7;")
-    a_("  const int tile = xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);")
-    a_(f"  const int e = tile * {LANES} + lane;")
-    a_("  const bool act = e < K;")
-    a_("  const int el = act ? e : K - 1;")
-    a_("  const size_t Ks = (size_t)K;")
+    _tile_prologue(a_)
+    _elem_prologue(a_)
     _phase_body(a_, t, g, Lp, pl, nw, staged)
+    a_("}")
+    return "\n".join(L) + "\n"
+
+
+def emit_trace(p: int) -> str:
+    """Trace kernel of order p: element-major traces of one field (the first phase
+    of a run and the rate operator need them before any phase has written them)."""
+    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    L = []
+    a_ = L.append
+    _header(a_, p, t, nw, staged, pl, "trace kernel")
+    a_("template <typename R>")
+    a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_trace_p{p}(const R* __restrict__ U,")
+    a_("    const R* __restrict__ MU, R* __restrict__ Tout, int K)")
+    a_("{")
+    _lds_decl(a_, t, staged)
+    _tile_prologue(a_)
+    _elem_prologue(a_)
+    if staged:
+        _stage_field(a_, t, nw, "U", "MU")
+        a_("  __syncthreads();")
+        _trace_stage(a_, t, g, pl, nw, "lds")
+    else:
+        _load_m(a_, "MU", "m")
+        _trace_stage(a_, t, g, pl, nw, ("U", "m"))
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -474,14 +579,12 @@ def emit_phase(p: int) -> str:
 def emit_batch(p: int) -> str:
     """Batched multi-mesh phase kernel of order p (FP32)."""
     t, g, Lp, nw, staged, pl = _kernel_setup(p)
-    N, NF = t.N, t.NF
     L = []
     a_ = L.append
-    a_(f"// Generated by gen/emit.py for order p = {p}: batched variant, {nw} waves per 64 elements.")
+    _header(a_, p, t, nw, staged, pl, "batched phase")
     a_("// One launch advances every slot (mesh) of this order.  Block b belongs to the last")
     a_("// slot s with tile0[s] <= b; blocks past the table, or of slots whose remaining")
     a_("// steps are exhausted at this sub-step, exit before any barrier.")
-    a_(f"static constexpr int kBatchWaves_p{p} = {nw};")
     a_("template <typename R>")
     a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
     a_("    const int* __restrict__ tile0, const int* __restrict__ nslots, int phase, int substep)")
@@ -497,23 +600,18 @@ def emit_batch(p: int) -> str:
     a_("  const R* __restrict__ U = (const R*)(phase ? sl.H : sl.E);")
     a_("  R* __restrict__ V = (R*)(phase ? sl.E : sl.H);")
     a_("  const R* __restrict__ MU = (const R*)(phase ? sl.MH : sl.ME);")
+    a_("  const R* __restrict__ MV = (const R*)(phase ? sl.ME : sl.MH);")
+    a_("  const R* __restrict__ Tin = (const R*)(phase ? sl.TH : sl.TE);")
+    a_("  R* __restrict__ Tout = (R*)(phase ? sl.TE : sl.TH);")
     a_("  const int* __restrict__ nbr = sl.nbr;")
     a_("  const R sdt = (R)(phase ? sl.dt : -sl.dt);")
     a_("  const R wall = phase ? R(1) : R(-1);")
     a_("  const int K = sl.K;")
-    a_(f"  const int lane = threadIdx.x & {LANES - 1};")
-    a_(f"  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);")
     a_("  const int tile = bid - tile0[lo];")
-    a_(f"  const int e = tile * {LANES} + lane;")
-    a_("  const bool act = e < K;")
-    a_("  const int el = act ? e : K - 1;")
-    a_("  const size_t Ks = (size_t)K;")
+    _elem_prologue(a_)
     _phase_body(a_, t, g, Lp, pl, nw, staged)
     a_("}")
     return "\n".join(L) + "\n"
-
-
-F64_MAX_ORDER = 4
 
 
 def _write_if_changed(path, src):
@@ -539,13 +637,27 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f'#include "phase_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_p{p}(const PhaseArgs<R>& a) {{",
-              f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.nbr, a.sdt, a.wall, a.K);",
+              f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
               "  return hipGetLastError();",
               "}",
               f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]
         if p <= F64_MAX_ORDER:
             tu.append(f"hipError_t dgm_launch_phase_p{p}_f64(const PhaseArgs<double>& a) {{ return launch_p{p}<double>(a); }}")
         units.append(_write_if_changed(os.path.join(outdir, f"phase_p{p}.hip"), "\n".join(tu) + "\n"))
+        _write_if_changed(os.path.join(outdir, f"trace_p{p}.inc"), emit_trace(p))
+        tt = [f"// Generated by gen/emit.py: trace kernel instantiation and launcher for order {p}.",
+              "#include <hip/hip_runtime.h>",
+              '#include "../launch.h"',
+              f'#include "trace_p{p}.inc"',
+              "template <typename R>",
+              f"static hipError_t launch_trace_p{p}(const TraceArgs<R>& a) {{",
+              f"  hipLaunchKernelGGL(dgm_trace_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.MU, a.T, a.K);",
+              "  return hipGetLastError();",
+              "}",
+              f"hipError_t dgm_launch_trace_p{p}_f32(const TraceArgs<float>& a) {{ return launch_trace_p{p}<float>(a); }}"]
+        if p <= F64_MAX_ORDER:
+            tt.append(f"hipError_t dgm_launch_trace_p{p}_f64(const TraceArgs<double>& a) {{ return launch_trace_p{p}<double>(a); }}")
+        units.append(_write_if_changed(os.path.join(outdir, f"trace_p{p}.hip"), "\n".join(tt) + "\n"))
         tb = [f"// Generated by gen/emit.py: batched launcher for order {p}.",
               "#include <hip/hip_runtime.h>",
               '#include "../launch.h"',
@@ -568,7 +680,13 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
         decl.append(f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a);")
         if p <= F64_MAX_ORDER:
             decl.append(f"hipError_t dgm_launch_phase_p{p}_f64(const PhaseArgs<double>& a);")
+    for p in orders:
+        decl.append(f"hipError_t dgm_launch_trace_p{p}_f32(const TraceArgs<float>& a);")
+        if p <= F64_MAX_ORDER:
+            decl.append(f"hipError_t dgm_launch_trace_p{p}_f64(const TraceArgs<double>& a);")
     lines += decl
+    lines.append("static hipError_t (*const kTraceF32[])(const TraceArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_trace_p{p}_f32" for p in orders) + "};")
+    lines.append("static hipError_t (*const kTraceF64[])(const TraceArgs<double>&) = {nullptr, " + ", ".join(f"dgm_launch_trace_p{p}_f64" for p in orders if p <= F64_MAX_ORDER) + "};")
     lines.append("static hipError_t (*const kPhaseF32[])(const PhaseArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f32" for p in orders) + "};")
     for p in orders:
         lines.append(f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a);")
