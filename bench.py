@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-nmax", type=int, default=10)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run three plain device copies of this many MiB (scale reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -181,6 +184,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if a.copy_mib > 0:
+        n = a.copy_mib * 2 ** 20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w, d, E0 = build_inputs()
     K, p = d["tets"].shape[0], w.p
     N = P.num_modes(p)

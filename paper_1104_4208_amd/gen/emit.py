@@ -154,32 +154,74 @@ def _lift_per_scalar(t, f, rows, Lp):
     return 2 * nnz + 2 * ncomp * len(rows) < ncomp * nnz
 
 
-def plan(p: int, nw: int = WAVES):
-    """Split one phase into trace jobs (face f, face rows: own traces) and
-    output jobs (volume rows, all three components), balanced over nw waves."""
+def _trace_job_cost(t, g, f, rows):
+    """Instruction estimate of a staged trace job: per streamed mode the LDS loads of
+    the components face f needs and the two tangential conversions, then two FMAs
+    per trace-table entry, and the stores of the traces."""
+    comps = sum(1 for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0)
+    conv = sum(1 for k in range(2) for c in range(3) if g[f][k][c] != 0.0)
+    cols = np.any(t.T[f][rows] != 0, axis=0)
+    return int(np.count_nonzero(cols) * (comps + conv + 2) + 2 * np.count_nonzero(t.T[f][rows]) + 2 * len(rows))
+
+
+def _out_job_cost(t, Lp, rows):
+    """Instruction estimate of an output job: per streamed mode the LDS loads of the
+    needed derivative-frame components and the curl FMAs; per face mode touched two
+    jump loads and the lift FMAs; the load-FMA-store update of 3 rows each."""
+    c = 0
+    for a in range(t.N):
+        hits = [[b for b in rows if t.D[d][b, a] != 0] for d in range(3)]
+        if not any(hits):
+            continue
+        need = set()
+        for k in range(3):
+            i, j = CYC[k]
+            if hits[i]:
+                need.add(j)
+            if hits[j]:
+                need.add(i)
+        c += len(need) + 2 + sum(2 * len(h) for h in hits)
+    for f in range(4):
+        ks = sum(1 for k in range(3) if np.any(Lp[f][k] != 0))
+        sub = t.T[f][:, rows]
+        nm = int(np.count_nonzero(np.any(sub != 0, axis=1)))
+        nnz = int(np.count_nonzero(sub))
+        per_row = 2 * nnz + 2 * ks * len(rows) if _lift_per_scalar(t, f, rows, Lp) else ks * (nnz + nm)
+        c += nm * 4 + per_row
+    return c + 9 * len(rows)
+
+
+def _split(items, cost_of, target, max_len):
+    """Consecutive chunks of items, each grown while its cost stays <= target."""
+    out, cur = [], []
+    for it in items:
+        if cur and (len(cur) >= max_len or cost_of(cur + [it]) > target):
+            out.append(cur)
+            cur = []
+        cur.append(it)
+    if cur:
+        out.append(cur)
+    return out
+
+
+def plan(p: int, nw: int = WAVES, granularity: int = 2):
+    """Split the trace stage into jobs (face f, face rows) and the update stage into
+    jobs (volume rows, all three components), each about 1/(granularity nw) of its
+    stage, and balance each stage over the nw waves (longest job first)."""
     t = TB.build(p)
     N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
+    tr_total = sum(_trace_job_cost(t, g, f, list(range(NF))) for f in range(4))
     tr_items, tr_cost = [], []
     for f in range(4):
-        for r0 in range(0, NF, TRACE_ROWS):
-            rows = list(range(r0, min(NF, r0 + TRACE_ROWS)))
-            own = 2 * np.count_nonzero(t.T[f][rows]) + 6 * np.count_nonzero(np.any(t.T[f][rows] != 0, axis=0))
+        for rows in _split(list(range(NF)), lambda r, f=f: _trace_job_cost(t, g, f, r),
+                           max(1, tr_total // (granularity * nw)), TRACE_ROWS):
             tr_items.append((f, rows))
-            tr_cost.append(int(own))
-    rc = []
-    for b in range(N):
-        c = sum(np.count_nonzero(t.D[d][b]) for d in range(3)) * 2 // 3 * 3 // 2
-        for f in range(4):
-            c += 2 * np.count_nonzero(t.T[f][:, b])
-        rc.append(c + 10)
-    out_items, out_cost = [], []
-    tot = sum(rc) + 9 * N * nw
-    for ch in _chunks(list(range(N)), rc, max(1, tot // (2 * nw))):
-        for r0 in range(0, len(ch), OUT_ROWS):
-            rows = ch[r0:r0 + OUT_ROWS]
-            out_items.append(rows)
-            out_cost.append(sum(rc[b] for b in rows) + 9 * N)
+            tr_cost.append(_trace_job_cost(t, g, f, rows))
+    out_total = _out_job_cost(t, Lp, list(range(N)))
+    out_items = _split(list(range(N)), lambda r: _out_job_cost(t, Lp, r),
+                       max(1, out_total // (granularity * nw)), OUT_ROWS)
+    out_cost = [_out_job_cost(t, Lp, r) for r in out_items]
     tr_w, tr_load = _assign(tr_items, tr_cost, nw)
     out_w, out_load = _assign(out_items, out_cost, nw)
     return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load)
@@ -202,16 +244,14 @@ def trace_strides(NF: int):
     return FS, 4 * FS
 
 
-def _trace_job(a_, t, g, f, rows, ind, src, sink):
+def _trace_job(a_, t, g, f, rows, ind, src):
     """Tangential traces tau_k = g_fk . w of one field on face f, face rows `rows`.
 
     src "lds": the field is staged in LDS (wl) in the derivative frame.
     src (ptr, mprefix): the field is read from global memory in the stored frame and
     converted on the fly with h_k = M g_fk (M held in registers mprefix00..22).
-    sink "jump": stage 1 of a phase; the neighbour traces already in jmp become the
-    jump (neighbour minus own), on walls (wall - 1) times the own trace.
-    sink "store": the traces go to the element-major staging area (row stride ES + 1)
-    that is copied out to the trace buffer."""
+    The traces go to the element-major staging area (row stride ES + 1) in LDS,
+    which is copied out to the trace buffer."""
     N, NF = t.N, t.NF
     FS, ES = trace_strides(NF)
     a_(ind + "{")
@@ -255,16 +295,9 @@ def _trace_job(a_, t, g, f, rows, ind, src, sink):
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
-    if sink == "jump":
-        a_(ind + f"  const int code = nbr[{f} * Ks + el];")
-        a_(ind + "  const R cw = code < 0 ? wall - R(1) : R(-1);")
-        for m in rows:
-            for k in range(2):
-                a_(ind + f"  jmp[({(f * 2 + k) * NF + m}) * {LANES} + lane] += cw * ts{k}_{m};")
-    else:
-        for m in rows:
-            for k in range(2):
-                a_(ind + f"  jmp[lane * {ES + 1} + {f * FS + k * NF + m}] = ts{k}_{m};")
+    for m in rows:
+        for k in range(2):
+            a_(ind + f"  jmp[lane * {ES + 1} + {f * FS + k * NF + m}] = ts{k}_{m};")
     a_(ind + "}")
 
 
@@ -273,6 +306,9 @@ def _output_job(a_, t, Lp, rows, ind, staged=False):
     derivative frame (one conversion per streamed mode) plus the lifted jumps."""
     N, NF = t.N, t.NF
     a_(ind + "{")
+    a_(ind + "  // old values of the updated rows, fetched before the arithmetic")
+    for b in rows:
+        a_(ind + "  const R " + ", ".join(f"vo{k}_{b} = V[({k * N + b}) * Ks + el]" for k in range(3)) + ";")
     a_(ind + "  R " + ", ".join(f"acc{k}_{b} = R(0)" for b in rows for k in range(3)) + ";")
     rowsM = {0: "m00 * {0} + m01 * {1} + m02 * {2}", 1: "m01 * {0} + m11 * {1} + m12 * {2}", 2: "m02 * {0} + m12 * {1} + m22 * {2}"}
     blocks = []
@@ -362,7 +398,7 @@ def _output_job(a_, t, Lp, rows, ind, staged=False):
     a_(ind + "  if (act) {")
     for b in rows:
         for k in range(3):
-            a_(ind + f"    V[({k * N + b}) * Ks + e] += sdt * acc{k}_{b};")
+            a_(ind + f"    V[({k * N + b}) * Ks + e] = vo{k}_{b} + sdt * acc{k}_{b};")
     a_(ind + "  }")
     a_(ind + "}")
 
@@ -385,18 +421,24 @@ def waves_for(p: int) -> int:
 
 
 def _stage_field(a_, t, nw, X, mp):
-    """wl = M X for the tile (M from the 6-component table mp): each wave converts
-    every nw-th mode of all 64 elements with coalesced loads."""
+    """wl = M X for the tile (M from the 6-component table mp): wave w converts modes
+    w, w + nw, ... of all 64 elements.  Every load of the wave is issued before the
+    first conversion (one memory round trip); the last mode index is clamped, so a
+    wave past the end rewrites mode N - 1 with the same values."""
     N = t.N
+    cnt = -(-N // nw)
     a_("  {")
     a_(f"    const R n00 = {mp}[0 * Ks + el], n01 = {mp}[1 * Ks + el], n02 = {mp}[2 * Ks + el];")
     a_(f"    const R n11 = {mp}[3 * Ks + el], n12 = {mp}[4 * Ks + el], n22 = {mp}[5 * Ks + el];")
-    a_(f"    for (int a = wave; a < {N}; a += {nw}) {{")
-    a_(f"      const R s0 = {X}[(size_t)a * Ks + el], s1 = {X}[(size_t)({N} + a) * Ks + el], s2 = {X}[(size_t)({2 * N} + a) * Ks + el];")
-    a_(f"      wl[(a) * {LANES} + lane] = n00 * s0 + n01 * s1 + n02 * s2;")
-    a_(f"      wl[({N} + a) * {LANES} + lane] = n01 * s0 + n11 * s1 + n12 * s2;")
-    a_(f"      wl[({2 * N} + a) * {LANES} + lane] = n02 * s0 + n12 * s1 + n22 * s2;")
-    a_("    }")
+    for i in range(cnt):
+        idx = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {N - 1})"
+        a_(f"    const int a{i} = {idx};")
+        a_(f"    const R s{i}_0 = {X}[(size_t)a{i} * Ks + el], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + el], "
+           f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + el];")
+    for i in range(cnt):
+        a_(f"    wl[a{i} * {LANES} + lane] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
+        a_(f"    wl[({N} + a{i}) * {LANES} + lane] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
+        a_(f"    wl[({2 * N} + a{i}) * {LANES} + lane] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
     a_("  }")
 
 
@@ -405,26 +447,40 @@ def _load_m(a_, mp, reg):
     a_(f"  const R {reg}11 = {mp}[3 * Ks + el], {reg}12 = {mp}[4 * Ks + el], {reg}22 = {mp}[5 * Ks + el];")
 
 
-def _neighbour_pass(a_, t, nw):
-    """jmp <- neighbour traces (0 on walls): per face 2 NF contiguous values of the
-    neighbour's face block, four per 16-byte load."""
+def _jump_pass(a_, t, nw):
+    """jmp <- jumps of the tangential traces of U, read from its trace buffer Tin:
+    neighbour minus own on interior faces, (wall - 1) times own on walls.  Per face
+    2 NF contiguous values of the own and of the neighbour's face block, four per
+    16-byte load.  Wave w takes chunks w, w + nw, ...; all codes are loaded first,
+    then all trace values (on walls the 'neighbour' load re-reads the own block), so
+    the pass costs two memory round trips.  The last chunk index is clamped; a wave
+    past the end rewrites the last chunk with the same values."""
     NF = t.NF
     FS, ES = trace_strides(NF)
     FQ = FS // 4
-    a_("  // neighbour traces from the other field's trace buffer (0 on walls)")
-    a_(f"  for (int q = wave; q < {4 * FQ}; q += {nw}) {{")
-    a_(f"    const int f = q / {FQ}, c = 4 * (q - f * {FQ});")
-    a_("    const int code = nbr[f * Ks + el];")
-    a_("    R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);")
-    a_("    if (code >= 0) {")
-    a_(f"      const R* s = (const R*)__builtin_assume_aligned(Tin + (size_t)(code >> 2) * {ES} + (code & 3) * {FS} + c, 16);")
-    a_("      v0 = s[0]; v1 = s[1]; v2 = s[2]; v3 = s[3];")
-    a_("    }")
-    a_(f"    R* d = jmp + (f * {2 * NF} + c) * {LANES} + lane;")
-    a_(f"    d[0] = v0;")
-    a_(f"    if (c + 1 < {2 * NF}) d[{LANES}] = v1;")
-    a_(f"    if (c + 2 < {2 * NF}) d[{2 * LANES}] = v2;")
-    a_(f"    if (c + 3 < {2 * NF}) d[{3 * LANES}] = v3;")
+    cnt = -(-4 * FQ // nw)
+    a_("  // jumps of the traces of U (own and neighbour face blocks of the trace buffer)")
+    a_("  {")
+    for i in range(cnt):
+        q = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {4 * FQ - 1})"
+        a_(f"    const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
+        a_(f"    const int code{i} = nbr[f{i} * Ks + el];")
+    for i in range(cnt):
+        a_(f"    const size_t src{i} = code{i} >= 0 ? (size_t)(code{i} >> 2) * {ES} + (code{i} & 3) * {FS} + c{i} "
+           f": (size_t)el * {ES} + f{i} * {FS} + c{i};")
+        a_(f"    const R* so{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)el * {ES} + f{i} * {FS} + c{i}, 16);")
+        a_(f"    const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + src{i}, 16);")
+        a_(f"    const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
+        a_(f"    const R n{i}_0 = sn{i}[0], n{i}_1 = sn{i}[1], n{i}_2 = sn{i}[2], n{i}_3 = sn{i}[3];")
+    for i in range(cnt):
+        a_(f"    {{")
+        a_(f"      const bool in = code{i} >= 0;")
+        a_(f"      const R cw = wall - R(1);")
+        a_(f"      R* d = jmp + (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
+        for j in range(4):
+            st = f"d[{j * LANES}] = in ? n{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
+            a_(f"      {st}" if j == 0 else f"      if (c{i} + {j} < {2 * NF}) {st}")
+        a_(f"    }}")
     a_("  }")
 
 
@@ -437,7 +493,7 @@ def _trace_stage(a_, t, g, pl, nw, src):
         a_(f"  if (wave == {w}) {{")
         for (f, rows) in pl["trace"][w]:
             a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ", src, "store")
+            _trace_job(a_, t, g, f, rows, "    ", src)
         a_("  }")
     a_("  __syncthreads();")
     a_("  {")
@@ -452,25 +508,14 @@ def _trace_stage(a_, t, g, pl, nw, src):
 
 def _phase_body(a_, t, g, Lp, pl, nw, staged):
     """Stages of one phase (shared by the single-mesh and the batched kernel):
-    0 stage U (derivative frame) and gather the neighbour traces, 1 own traces ->
-    jumps, 2 curl + lift + update of V, 3 (if Tout) traces of the new V."""
-    N, NF = t.N, t.NF
+    1 stage U (derivative frame) and form the trace jumps from the trace buffer,
+    2 curl + lift + update of V, 3 (if Tout) traces of the new V."""
     if staged:
-        a_("  // stage 0: the tile's own field in the derivative frame, w = M S, into LDS")
+        a_("  // stage 1: the tile's own field in the derivative frame, w = M S, into LDS")
         _stage_field(a_, t, nw, "U", "MU")
-        src = "lds"
     else:
         _load_m(a_, "MU", "m")
-        src = ("U", "m")
-    _neighbour_pass(a_, t, nw)
-    a_("  __syncthreads();")
-    a_("  // stage 1: jumps of the tangential traces (neighbour minus own) in LDS")
-    for w in range(nw):
-        a_(f"  if (wave == {w}) {{")
-        for (f, rows) in pl["trace"][w]:
-            a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ", src, "jump")
-        a_("  }")
+    _jump_pass(a_, t, nw)
     a_("  __syncthreads();")
     a_("  // stage 2: curl and lifted jumps, component-separable update")
     for w in range(nw):
