@@ -417,7 +417,7 @@ def staged_fits(p: int, elem_bytes: int = 4) -> bool:
 
 
 def waves_for(p: int) -> int:
-    return 8 if p >= 4 else 4
+    return 16 if p >= 5 else (8 if p >= 4 else 4)
 
 
 def _stage_field(a_, t, nw, X, mp):
