@@ -97,6 +97,8 @@ TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
 
 
 PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
+LDS_PREFIXES = ("wl[", "jmp[")
+LDS_GROUP = 16    # LDS-sourced mode blocks per basic block
 
 
 class _Stream:
@@ -118,6 +120,27 @@ class _Stream:
         body(names) -> list of statements using the loaded values."""
         a_, ind, tag = self.a_, self.ind, self.tag
         if not blocks:
+            return
+        if all(expr.startswith(LDS_PREFIXES) for ld, _ in blocks for expr in ld):
+            # LDS operands (short latency): LDS_GROUP mode blocks per basic block, all
+            # their loads first; the compiler schedules inside the group, and no value
+            # crosses a group boundary except the accumulators
+            a_(ind + "size_t o = 0;")
+            for g0 in range(0, len(blocks), LDS_GROUP):
+                grp = blocks[g0:g0 + LDS_GROUP]
+                a_(ind + "asm volatile(\"\" : \"+s\"(o));")
+                a_(ind + "if (o == 0) {")
+                names = []
+                for gi, (ld, body) in enumerate(grp):
+                    nm = [f"x{gi}_{q}" for q in range(len(ld))]
+                    names.append(nm)
+                    a_(ind + "  const R " + ", ".join(f"{n} = {e}" for n, e in zip(nm, ld)) + ";")
+                for gi, (ld, body) in enumerate(grp):
+                    a_(ind + "  {")
+                    for st in body(names[gi]):
+                        a_(ind + "    " + st)
+                    a_(ind + "  }")
+                a_(ind + "}")
             return
         nl = max(len(ld) for ld, _ in blocks)
         slots = [[f"{tag}{r}_{q}" for q in range(nl)] for r in range(PREFETCH)]
