@@ -93,7 +93,7 @@ def _assign(jobs, costs, nw):
     return out, load
 
 
-TRACE_ROWS = 14   # face modes per trace job (bounds the job's accumulators)
+TRACE_ROWS = 32   # face modes per trace job (bounds the job's accumulators)
 
 
 PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
@@ -165,7 +165,7 @@ class _Stream:
             a_(ind + "}")
 
 
-OUT_ROWS = 16     # volume modes per output job (3 components each)
+OUT_ROWS = 32     # volume modes per output job (3 components each)
 CYC = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
 
 
@@ -214,39 +214,80 @@ def _out_job_cost(t, Lp, rows):
     return c + 9 * len(rows)
 
 
-def _split(items, cost_of, target, max_len):
-    """Consecutive chunks of items, each grown while its cost stays <= target."""
-    out, cur = [], []
-    for it in items:
-        if cur and (len(cur) >= max_len or cost_of(cur + [it]) > target):
-            out.append(cur)
-            cur = []
-        cur.append(it)
-    if cur:
-        out.append(cur)
-    return out
+def _balance(items, single, bin_cost, nw, cap, sweeps=4):
+    """Partition items over nw bins: greedy (largest item first, into the bin whose
+    cost grows least in absolute terms of its new load), then moves of single items
+    off the most loaded bin while that lowers the maximum.  bin_cost(list) prices a
+    bin; cap(list) says whether a bin may hold the list."""
+    bins = [[] for _ in range(nw)]
+    load = [0] * nw
+    for it in sorted(items, key=lambda x: -single(x)):
+        best = None
+        for w in range(nw):
+            cand = bins[w] + [it]
+            if not cap(cand):
+                continue
+            c = bin_cost(cand)
+            if best is None or c < best[0]:
+                best = (c, w)
+        c, w = best
+        bins[w].append(it)
+        load[w] = c
+    for _ in range(sweeps * len(items)):
+        hi = max(range(nw), key=lambda w: load[w])
+        moved = False
+        for it in sorted(bins[hi], key=single):
+            rest = [x for x in bins[hi] if x != it]
+            c_hi = bin_cost(rest)
+            for w in sorted(range(nw), key=lambda w: load[w]):
+                if w == hi or not cap(bins[w] + [it]):
+                    continue
+                c_w = bin_cost(bins[w] + [it])
+                if max(c_hi, c_w) < load[hi]:
+                    bins[hi], load[hi] = rest, c_hi
+                    bins[w].append(it)
+                    load[w] = c_w
+                    moved = True
+                    break
+            if moved:
+                break
+        if not moved:
+            break
+    return bins, load
 
 
-def plan(p: int, nw: int = WAVES, granularity: int = 2):
-    """Split the trace stage into jobs (face f, face rows) and the update stage into
-    jobs (volume rows, all three components), each about 1/(granularity nw) of its
-    stage, and balance each stage over the nw waves (longest job first)."""
+def plan(p: int, nw: int = WAVES):
+    """One output job per wave (volume rows, all three components) and per wave one
+    trace job per face it touches (face rows), balanced over the nw waves with the
+    instruction estimates above: every job streams its operands from LDS once, so
+    few large jobs keep the LDS traffic low."""
     t = TB.build(p)
     N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
-    tr_total = sum(_trace_job_cost(t, g, f, list(range(NF))) for f in range(4))
-    tr_items, tr_cost = [], []
-    for f in range(4):
-        for rows in _split(list(range(NF)), lambda r, f=f: _trace_job_cost(t, g, f, r),
-                           max(1, tr_total // (granularity * nw)), TRACE_ROWS):
-            tr_items.append((f, rows))
-            tr_cost.append(_trace_job_cost(t, g, f, rows))
-    out_total = _out_job_cost(t, Lp, list(range(N)))
-    out_items = _split(list(range(N)), lambda r: _out_job_cost(t, Lp, r),
-                       max(1, out_total // (granularity * nw)), OUT_ROWS)
-    out_cost = [_out_job_cost(t, Lp, r) for r in out_items]
-    tr_w, tr_load = _assign(tr_items, tr_cost, nw)
-    out_w, out_load = _assign(out_items, out_cost, nw)
+
+    def tr_bin(items):
+        by_f = {}
+        for f, m in items:
+            by_f.setdefault(f, []).append(m)
+        return sum(_trace_job_cost(t, g, f, sorted(ms)) for f, ms in by_f.items())
+
+    def tr_cap(items):
+        by_f = {}
+        for f, m in items:
+            by_f[f] = by_f.get(f, 0) + 1
+        return max(by_f.values()) <= TRACE_ROWS
+
+    tr_items = [(f, m) for f in range(4) for m in range(NF) if np.any(t.T[f][m] != 0)]
+    tb, tr_load = _balance(tr_items, lambda x: tr_bin([x]), tr_bin, nw, tr_cap)
+    tr_w = []
+    for items in tb:
+        by_f = {}
+        for f, m in items:
+            by_f.setdefault(f, []).append(m)
+        tr_w.append([(f, sorted(ms)) for f, ms in sorted(by_f.items())])
+    ob, out_load = _balance(list(range(N)), lambda b: _out_job_cost(t, Lp, [b]),
+                            lambda rows: _out_job_cost(t, Lp, sorted(rows)), nw, lambda rows: len(rows) <= OUT_ROWS)
+    out_w = [[sorted(rows)] if rows else [] for rows in ob]
     return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load)
 
 
@@ -440,28 +481,35 @@ def staged_fits(p: int, elem_bytes: int = 4) -> bool:
 
 
 def waves_for(p: int) -> int:
-    return 16 if p >= 5 else (8 if p >= 4 else 4)
+    return 8 if p >= 4 else 4
+
+
+def _stage_parts(t, nw, X, mp):
+    """wl = M X for the tile (M from the 6-component table mp): wave w converts modes
+    w, w + nw, ... of all 64 elements.  Returns (loads, stores): every load of the
+    wave is issued before the first conversion (one memory round trip); the last mode
+    index is clamped, so a wave past the end rewrites mode N - 1 with the same values."""
+    N = t.N
+    cnt = -(-N // nw)
+    ld = [f"const R n00 = {mp}[0 * Ks + el], n01 = {mp}[1 * Ks + el], n02 = {mp}[2 * Ks + el];",
+          f"const R n11 = {mp}[3 * Ks + el], n12 = {mp}[4 * Ks + el], n22 = {mp}[5 * Ks + el];"]
+    st = []
+    for i in range(cnt):
+        idx = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {N - 1})"
+        ld.append(f"const int a{i} = {idx};")
+        ld.append(f"const R s{i}_0 = {X}[(size_t)a{i} * Ks + el], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + el], "
+                  f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + el];")
+        st.append(f"wl[a{i} * {LANES} + lane] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
+        st.append(f"wl[({N} + a{i}) * {LANES} + lane] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
+        st.append(f"wl[({2 * N} + a{i}) * {LANES} + lane] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
+    return ld, st
 
 
 def _stage_field(a_, t, nw, X, mp):
-    """wl = M X for the tile (M from the 6-component table mp): wave w converts modes
-    w, w + nw, ... of all 64 elements.  Every load of the wave is issued before the
-    first conversion (one memory round trip); the last mode index is clamped, so a
-    wave past the end rewrites mode N - 1 with the same values."""
-    N = t.N
-    cnt = -(-N // nw)
+    ld, st = _stage_parts(t, nw, X, mp)
     a_("  {")
-    a_(f"    const R n00 = {mp}[0 * Ks + el], n01 = {mp}[1 * Ks + el], n02 = {mp}[2 * Ks + el];")
-    a_(f"    const R n11 = {mp}[3 * Ks + el], n12 = {mp}[4 * Ks + el], n22 = {mp}[5 * Ks + el];")
-    for i in range(cnt):
-        idx = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {N - 1})"
-        a_(f"    const int a{i} = {idx};")
-        a_(f"    const R s{i}_0 = {X}[(size_t)a{i} * Ks + el], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + el], "
-           f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + el];")
-    for i in range(cnt):
-        a_(f"    wl[a{i} * {LANES} + lane] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
-        a_(f"    wl[({N} + a{i}) * {LANES} + lane] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
-        a_(f"    wl[({2 * N} + a{i}) * {LANES} + lane] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
+    for l in ld + st:
+        a_("    " + l)
     a_("  }")
 
 
@@ -470,41 +518,40 @@ def _load_m(a_, mp, reg):
     a_(f"  const R {reg}11 = {mp}[3 * Ks + el], {reg}12 = {mp}[4 * Ks + el], {reg}22 = {mp}[5 * Ks + el];")
 
 
-def _jump_pass(a_, t, nw):
-    """jmp <- jumps of the tangential traces of U, read from its trace buffer Tin:
-    neighbour minus own on interior faces, (wall - 1) times own on walls.  Per face
-    2 NF contiguous values of the own and of the neighbour's face block, four per
-    16-byte load.  Wave w takes chunks w, w + nw, ...; all codes are loaded first,
-    then all trace values (on walls the 'neighbour' load re-reads the own block), so
-    the pass costs two memory round trips.  The last chunk index is clamped; a wave
-    past the end rewrites the last chunk with the same values."""
+def _jump_parts(t, nw):
+    """Jumps of the tangential traces of U, read from its trace buffer Tin: neighbour
+    minus own on interior faces, (wall - 1) times own on walls.  Per face 2 NF
+    contiguous values of the own and of the neighbour's face block, four per 16-byte
+    load.  Wave w takes chunks w, w + nw, ...  Returns (codes, loads, stores): the
+    neighbour codes, then every trace load (on walls the 'neighbour' load re-reads the
+    own block), then the LDS stores.  The last chunk index is clamped; a wave past the
+    end rewrites the last chunk with the same values."""
     NF = t.NF
     FS, ES = trace_strides(NF)
     FQ = FS // 4
     cnt = -(-4 * FQ // nw)
-    a_("  // jumps of the traces of U (own and neighbour face blocks of the trace buffer)")
-    a_("  {")
+    codes, loads, stores = [], [], []
     for i in range(cnt):
         q = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {4 * FQ - 1})"
-        a_(f"    const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
-        a_(f"    const int code{i} = nbr[f{i} * Ks + el];")
+        codes.append(f"const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
+        codes.append(f"const int code{i} = nbr[f{i} * Ks + el];")
     for i in range(cnt):
-        a_(f"    const size_t src{i} = code{i} >= 0 ? (size_t)(code{i} >> 2) * {ES} + (code{i} & 3) * {FS} + c{i} "
-           f": (size_t)el * {ES} + f{i} * {FS} + c{i};")
-        a_(f"    const R* so{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)el * {ES} + f{i} * {FS} + c{i}, 16);")
-        a_(f"    const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + src{i}, 16);")
-        a_(f"    const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
-        a_(f"    const R n{i}_0 = sn{i}[0], n{i}_1 = sn{i}[1], n{i}_2 = sn{i}[2], n{i}_3 = sn{i}[3];")
+        loads.append(f"const size_t src{i} = code{i} >= 0 ? (size_t)(code{i} >> 2) * {ES} + (code{i} & 3) * {FS} + c{i} "
+                     f": (size_t)el * {ES} + f{i} * {FS} + c{i};")
+        loads.append(f"const R* so{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)el * {ES} + f{i} * {FS} + c{i}, 16);")
+        loads.append(f"const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + src{i}, 16);")
+        loads.append(f"const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
+        loads.append(f"const R t{i}_0 = sn{i}[0], t{i}_1 = sn{i}[1], t{i}_2 = sn{i}[2], t{i}_3 = sn{i}[3];")
+    stores.append("const R cw = wall - R(1);")
     for i in range(cnt):
-        a_(f"    {{")
-        a_(f"      const bool in = code{i} >= 0;")
-        a_(f"      const R cw = wall - R(1);")
-        a_(f"      R* d = jmp + (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
+        stores.append(f"{{")
+        stores.append(f"  const bool in = code{i} >= 0;")
+        stores.append(f"  R* d = jmp + (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
         for j in range(4):
-            st = f"d[{j * LANES}] = in ? n{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
-            a_(f"      {st}" if j == 0 else f"      if (c{i} + {j} < {2 * NF}) {st}")
-        a_(f"    }}")
-    a_("  }")
+            st = f"d[{j * LANES}] = in ? t{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
+            stores.append(f"  {st}" if j == 0 else f"  if (c{i} + {j} < {2 * NF}) {st}")
+        stores.append(f"}}")
+    return codes, loads, stores
 
 
 def _trace_stage(a_, t, g, pl, nw, src):
@@ -533,12 +580,19 @@ def _phase_body(a_, t, g, Lp, pl, nw, staged):
     """Stages of one phase (shared by the single-mesh and the batched kernel):
     1 stage U (derivative frame) and form the trace jumps from the trace buffer,
     2 curl + lift + update of V, 3 (if Tout) traces of the new V."""
+    codes, tl, ts = _jump_parts(t, nw)
     if staged:
-        a_("  // stage 1: the tile's own field in the derivative frame, w = M S, into LDS")
-        _stage_field(a_, t, nw, "U", "MU")
+        sl, ss = _stage_parts(t, nw, "U", "MU")
     else:
         _load_m(a_, "MU", "m")
-    _jump_pass(a_, t, nw)
+        sl, ss = [], []
+    a_("  // stage 1: the tile's own field in the derivative frame, w = M S, into LDS, and the")
+    a_("  // jumps of the traces of U (own and neighbour face blocks of its trace buffer);")
+    a_("  // neighbour codes first, then the field and trace loads, then the LDS stores")
+    a_("  {")
+    for l in codes + sl + tl + ss + ts:
+        a_("    " + l)
+    a_("  }")
     a_("  __syncthreads();")
     a_("  // stage 2: curl and lifted jumps, component-separable update")
     for w in range(nw):
