@@ -46,6 +46,8 @@ int fail(int code, const std::string& msg) {
 
 int num_modes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 int num_face_modes(int p) { return (p + 1) * (p + 2) / 2; }
+// Values of one field's trace buffer: whole 64-element tiles (the last one padded).
+size_t trace_words(int64_t K, int p) { return (size_t)((K + 63) / 64) * 64 * trace_elem_stride(num_face_modes(p)); }
 
 // ---------------------------------------------------------------- kernels
 // X_m <- P X_m for every mode m of every element, P = (Minv A) (to the stored
@@ -202,7 +204,7 @@ int ensure_scratch(dgm_mesh* m, size_t bytes) {
 // Trace buffers of both fields (E, then H) in precision R, grown on demand.
 template <typename R>
 int ensure_traces(dgm_mesh* m, R** TE, R** TH) {
-  const size_t per = (size_t)m->K * trace_elem_stride(num_face_modes(m->p));
+  const size_t per = trace_words(m->K, m->p);
   const size_t bytes = 2 * per * sizeof(R);
   if (m->T_bytes < bytes) {
     if (m->d_T) HIP_TRY(hipFree(m->d_T));
@@ -936,7 +938,7 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
     bs.MH = q.m->d_M32[1];
     bs.nbr = q.m->d_nbr;
     bs.TE = q.m->d_T;
-    bs.TH = static_cast<const float*>(q.m->d_T) + (size_t)q.m->K * trace_elem_stride(num_face_modes(p));
+    bs.TH = static_cast<const float*>(q.m->d_T) + trace_words(q.m->K, p);
     bs.K = (int)q.m->K;
     bs.steps_left = (int)std::min<int64_t>(b->chunk, q.left);
     bs.dt = q.dt;

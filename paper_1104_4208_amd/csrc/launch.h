@@ -2,9 +2,11 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-// Element-major trace buffer of one field: per element four faces, each holding the
-// two tangential traces on the NF face modes (tangent major) padded to a multiple of
-// four values, so a neighbour's face block is read with 16-byte loads.
+// Trace buffer of one field: per element four faces, each holding the two tangential
+// traces on the NF face modes (tangent major) padded to a multiple of four values.
+// Tiles of 64 elements are contiguous; inside a tile, chunk j (four consecutive
+// values of one face) of lane l sits at (j * 64 + l) * 4, so a workgroup stores its
+// traces coalesced and a neighbour's chunk is one 16-byte load.
 constexpr int trace_face_stride(int NF) { return (2 * NF + 3) & ~3; }
 constexpr int trace_elem_stride(int NF) { return 4 * trace_face_stride(NF); }
 
@@ -15,8 +17,8 @@ struct PhaseArgs {
   const R* MU;      // (6,K) symmetric conversion of U into the derivative frame
   const R* MV;      // (6,K) the same for V (traces of the updated V)
   const int* nbr;   // (4,K) neighbour code nb*4 + neighbour's local face, -1 on walls
-  const R* Tin;     // (K, ES) traces of U (written by the trace kernel or the previous phase)
-  R* Tout;          // (K, ES) traces of the updated V, or nullptr to skip them
+  const R* Tin;     // traces of U (written by the trace kernel or the previous phase)
+  R* Tout;          // traces of the updated V, or nullptr to skip them
   R sdt;            // signed step: -dt (H update) or +dt (E update); -1/+1 for a bare rate
   R wall;           // ghost factor on walls: -1 (E_nb = -E) or +1 (H_nb = H)
   int K;            // number of elements
@@ -28,7 +30,7 @@ template <typename R>
 struct TraceArgs {
   const R* U;       // (3,N,K) stored-frame field
   const R* MU;      // (6,K) its conversion into the derivative frame
-  R* T;             // (K, ES) traces out
+  R* T;             // traces out (whole tiles)
   int K;
   int blocks;       // ceil(K / 64)
   hipStream_t stream;
@@ -41,8 +43,8 @@ struct BatchSlot {
   const void* ME;   // (6,K) conversion of E into the derivative frame
   const void* MH;   // (6,K) conversion of H
   const int* nbr;   // (4,K)
-  const void* TE;   // (K, ES) traces of E, kept current by every E update
-  const void* TH;   // (K, ES) traces of H, written by every H update
+  const void* TE;   // traces of E, kept current by every E update
+  const void* TH;   // traces of H, written by every H update
   int K;
   int steps_left;   // sub-steps of the current launch this slot still takes
   double dt;

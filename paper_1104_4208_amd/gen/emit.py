@@ -47,121 +47,53 @@ def _fma(acc, coef, x):
     return f"{acc} += {_lit(coef)} * {x};"
 
 
-def _dot(gv, w, name):
-    terms = []
-    for c, x in zip(gv, w):
-        if c == 0.0:
-            continue
-        if c == 1.0:
-            terms.append(x)
-        elif c == -1.0:
-            terms.append(f"-{x}")
-        else:
-            terms.append(f"{_lit(c)} * {x}")
-    return f"const R {name} = {' + '.join(terms) if terms else 'R(0)'};"
-
-
-WAVES = 4
 LANES = 64
-LDS_BUDGET = 150 * 1024  # bytes of LDS one workgroup may use for the staged field and jumps
+LDS_BUDGET = 160 * 1024  # bytes of LDS per compute unit
 F64_MAX_ORDER = 4   # highest order also instantiated in FP64 (compile time grows steeply with p)
-
-
-def _chunks(items, costs, max_cost):
-    """Split an ordered list into consecutive chunks whose summed cost stays <= max_cost."""
-    out, cur, c = [], [], 0
-    for it, w in zip(items, costs):
-        if cur and c + w > max_cost:
-            out.append(cur)
-            cur, c = [], 0
-        cur.append(it)
-        c += w
-    if cur:
-        out.append(cur)
-    return out
-
-
-def _assign(jobs, costs, nw):
-    """Longest-processing-time assignment of jobs to nw waves; returns per-wave job lists."""
-    order = sorted(range(len(jobs)), key=lambda i: -costs[i])
-    load = [0] * nw
-    out = [[] for _ in range(nw)]
-    for i in order:
-        w = min(range(nw), key=lambda k: load[k])
-        out[w].append(jobs[i])
-        load[w] += costs[i]
-    return out, load
 
 
 TRACE_ROWS = 32   # face modes per trace job (bounds the job's accumulators)
 
 
-PREFETCH = 3      # mode blocks of loads issued ahead of use in a stream
-LDS_PREFIXES = ("wl[", "jmp[")
-LDS_GROUP = 16    # LDS-sourced mode blocks per basic block
+LDS_GROUP = 8     # mode blocks per basic block in a stream
+VO_EARLY_MAX = 96  # registers the old values plus rates of a wave's rows may hold
+                   # through the lift (else the old values are read at the update)
 
 
 class _Stream:
-    """Emit a stream of mode blocks as separate basic blocks with explicit prefetch.
+    """Emit a stream of mode blocks whose operands come from LDS.
 
-    Every block sits behind an opaque uniform branch (an offset that is zero but
-    hidden from the compiler by an empty asm statement), so instruction
-    scheduling stays inside one block and register pressure stays bounded; the
-    loads of block b + PREFETCH are issued inside block b into a small ring of
-    registers, which keeps memory latency hidden without hoisting every load of
-    the stream to its start.
+    LDS_GROUP blocks share one basic block, behind an opaque uniform branch (an
+    offset that is zero but hidden from the compiler by an empty asm statement):
+    the loads of a group are issued first and the compiler schedules inside the
+    group, while register pressure stays bounded by the group size; no value
+    crosses a group boundary except the accumulators.
     """
 
     def __init__(self, a_, ind, tag):
         self.a_, self.ind, self.tag = a_, ind, tag
 
     def emit(self, blocks):
-        """blocks: list of (loads, body) with loads = [load expressions, may use o] and
+        """blocks: list of (loads, body) with loads = [LDS load expressions] and
         body(names) -> list of statements using the loaded values."""
-        a_, ind, tag = self.a_, self.ind, self.tag
+        a_, ind = self.a_, self.ind
         if not blocks:
             return
-        if all(expr.startswith(LDS_PREFIXES) for ld, _ in blocks for expr in ld):
-            # LDS operands (short latency): LDS_GROUP mode blocks per basic block, all
-            # their loads first; the compiler schedules inside the group, and no value
-            # crosses a group boundary except the accumulators
-            a_(ind + "size_t o = 0;")
-            for g0 in range(0, len(blocks), LDS_GROUP):
-                grp = blocks[g0:g0 + LDS_GROUP]
-                a_(ind + "asm volatile(\"\" : \"+s\"(o));")
-                a_(ind + "if (o == 0) {")
-                names = []
-                for gi, (ld, body) in enumerate(grp):
-                    nm = [f"x{gi}_{q}" for q in range(len(ld))]
-                    names.append(nm)
-                    a_(ind + "  const R " + ", ".join(f"{n} = {e}" for n, e in zip(nm, ld)) + ";")
-                for gi, (ld, body) in enumerate(grp):
-                    a_(ind + "  {")
-                    for st in body(names[gi]):
-                        a_(ind + "    " + st)
-                    a_(ind + "  }")
-                a_(ind + "}")
-            return
-        nl = max(len(ld) for ld, _ in blocks)
-        slots = [[f"{tag}{r}_{q}" for q in range(nl)] for r in range(PREFETCH)]
-        a_(ind + "R " + ", ".join(f"{v} = R(0)" for r in slots for v in r) + ";")
         a_(ind + "size_t o = 0;")
-        for bi in range(min(PREFETCH, len(blocks))):
-            for q, expr in enumerate(blocks[bi][0]):
-                a_(ind + f"{slots[bi][q]} = {expr};")
-        for bi, (ld, body) in enumerate(blocks):
-            r = bi % PREFETCH
+        for g0 in range(0, len(blocks), LDS_GROUP):
+            grp = blocks[g0:g0 + LDS_GROUP]
             a_(ind + "asm volatile(\"\" : \"+s\"(o));")
             a_(ind + "if (o == 0) {")
-            names = [f"x{q}" for q in range(len(ld))]
-            for q in range(len(ld)):
-                a_(ind + f"  const R {names[q]} = {slots[r][q]};")
-            nxt = bi + PREFETCH
-            if nxt < len(blocks):
-                for q, expr in enumerate(blocks[nxt][0]):
-                    a_(ind + f"  {slots[r][q]} = {expr};")
-            for st in body(names):
-                a_(ind + "  " + st)
+            names = []
+            for gi, (ld, body) in enumerate(grp):
+                nm = [f"x{gi}_{q}" for q in range(len(ld))]
+                names.append(nm)
+                a_(ind + "  const R " + ", ".join(f"{n} = {e}" for n, e in zip(nm, ld)) + ";")
+            for gi, (ld, body) in enumerate(grp):
+                a_(ind + "  {")
+                for st in body(names[gi]):
+                    a_(ind + "    " + st)
+                a_(ind + "  }")
             a_(ind + "}")
 
 
@@ -256,7 +188,7 @@ def _balance(items, single, bin_cost, nw, cap, sweeps=4):
     return bins, load
 
 
-def plan(p: int, nw: int = WAVES):
+def plan(p: int, nw: int):
     """One output job per wave (volume rows, all three components) and per wave one
     trace job per face it touches (face rows), balanced over the nw waves with the
     instruction estimates above: every job streams its operands from LDS once, so
@@ -291,144 +223,122 @@ def plan(p: int, nw: int = WAVES):
     return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load)
 
 
-def _hvec(a_, ind, g, f, M, name):
-    """h = M g for the two tangential directions of face f: tau = h . S."""
-    m = {(0, 0): M + "00", (0, 1): M + "01", (0, 2): M + "02", (1, 1): M + "11", (1, 2): M + "12", (2, 2): M + "22"}
-    sym = lambda r, c: m[(min(r, c), max(r, c))]
-    for k in range(2):
-        for r in range(3):
-            terms = [f"{_lit(g[f][k][c])} * {sym(r, c)}" for c in range(3) if g[f][k][c] != 0.0]
-            a_(ind + f"const R {name}{k}{r} = {' + '.join(terms) if terms else 'R(0)'};")
-
-
 def trace_strides(NF: int):
-    """Element-major trace buffer: per element four faces of FS values (2 NF traces,
-    tangent k major, padded to a multiple of four), element stride ES = 4 FS."""
+    """Trace buffer of one field: per element four faces of FS values (the 2 NF
+    traces, tangent major, padded to a multiple of four), ES = 4 FS per element.
+    Tile-blocked and quad-interleaved: for the 64 elements of a tile, the four
+    values of chunk q (= face f, values 4j..4j+3) of lane l sit at
+    ((f FQ + j) 64 + l) 4, so a tile's threads store coalesced and a neighbour's
+    chunk is one 16-byte load."""
     FS = (2 * NF + 3) & ~3
     return FS, 4 * FS
 
 
-def _trace_job(a_, t, g, f, rows, ind, src):
-    """Tangential traces tau_k = g_fk . w of one field on face f, face rows `rows`.
-
-    src "lds": the field is staged in LDS (wl) in the derivative frame.
-    src (ptr, mprefix): the field is read from global memory in the stored frame and
-    converted on the fly with h_k = M g_fk (M held in registers mprefix00..22).
-    The traces go to the element-major staging area (row stride ES + 1) in LDS,
-    which is copied out to the trace buffer."""
-    N, NF = t.N, t.NF
+def _trace_index(NF, f, c, lane="lane"):
     FS, ES = trace_strides(NF)
+    FQ = FS // 4
+    return f"(({f * FQ + c // 4}) * {LANES} + {lane}) * 4 + {c % 4}"
+
+
+def _trace_job(a_, t, g, f, rows, ind):
+    """Tangential traces tau_k = g_fk . w on face f, face rows `rows`, of the field
+    staged in LDS (derivative frame), stored to the tile's block of Tout."""
+    N, NF = t.N, t.NF
     a_(ind + "{")
     a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
-    staged = src == "lds"
-    if not staged:
-        ptr, mp = src
-        _hvec(a_, ind + "  ", g, f, mp, "h")
     blocks = []
     for a in range(N):
         ms = [m for m in rows if t.T[f][m, a] != 0]
         if not ms:
             continue
-        if staged:
-            comps = [c for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0]
+        comps = [c for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0]
 
-            def body(x, a=a, ms=ms, comps=comps):
-                xs = dict(zip(comps, x))
-                out = []
-                for k in range(2):
-                    terms = [(g[f][k][c], xs[c]) for c in comps if g[f][k][c] != 0.0]
-                    out.append(f"const R q{k} = " + " + ".join(
-                        (v if c == 1.0 else (f"-{v}" if c == -1.0 else f"{_lit(c)} * {v}")) for c, v in terms) + ";")
-                for m in ms:
-                    for k in range(2):
-                        out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
-                return out
-
-            blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in comps], body))
-            continue
-
-        def body(x, a=a, ms=ms):
-            out = [f"const R q0 = h00 * {x[0]} + h01 * {x[1]} + h02 * {x[2]}, q1 = h10 * {x[0]} + h11 * {x[1]} + h12 * {x[2]};"]
+        def body(x, a=a, ms=ms, comps=comps):
+            xs = dict(zip(comps, x))
+            out = []
+            for k in range(2):
+                terms = [(g[f][k][c], xs[c]) for c in comps if g[f][k][c] != 0.0]
+                out.append(f"const R q{k} = " + " + ".join(
+                    (v if c == 1.0 else (f"-{v}" if c == -1.0 else f"{_lit(c)} * {v}")) for c, v in terms) + ";")
             for m in ms:
                 for k in range(2):
                     out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
             return out
 
-        blocks.append(([f"{ptr}[o + ({a}) * Ks + el]", f"{ptr}[o + ({N + a}) * Ks + el]",
-                        f"{ptr}[o + ({2 * N + a}) * Ks + el]"], body))
+        blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in comps], body))
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
     for m in rows:
         for k in range(2):
-            a_(ind + f"  jmp[lane * {ES + 1} + {f * FS + k * NF + m}] = ts{k}_{m};")
+            a_(ind + f"  Tout[tb + {_trace_index(NF, f, k * NF + m)}] = ts{k}_{m};")
     a_(ind + "}")
 
 
-def _output_job(a_, t, Lp, rows, ind, staged=False):
-    """All three components of the update on volume rows `rows`: curl in the
-    derivative frame (one conversion per streamed mode) plus the lifted jumps."""
-    N, NF = t.N, t.NF
+def _curl_job(a_, t, rows, ind):
+    """Curl part of the rates of the wave's rows (all three components, derivative
+    frame from LDS) into the accumulator slots 0..len(rows)-1."""
+    N = t.N
     a_(ind + "{")
-    a_(ind + "  // old values of the updated rows, fetched before the arithmetic")
-    for b in rows:
-        a_(ind + "  const R " + ", ".join(f"vo{k}_{b} = V[({k * N + b}) * Ks + el]" for k in range(3)) + ";")
-    a_(ind + "  R " + ", ".join(f"acc{k}_{b} = R(0)" for b in rows for k in range(3)) + ";")
-    rowsM = {0: "m00 * {0} + m01 * {1} + m02 * {2}", 1: "m01 * {0} + m11 * {1} + m12 * {2}", 2: "m02 * {0} + m12 * {1} + m22 * {2}"}
     blocks = []
     for a in range(N):
-        hits = {d: [b for b in rows if t.D[d][b, a] != 0] for d in range(3)}
+        hits = {d: [(j, b) for j, b in enumerate(rows) if t.D[d][b, a] != 0] for d in range(3)}
         if not any(hits.values()):
             continue
         need = set()
         for k in range(3):
-            i, j = CYC[k]
+            i, jj = CYC[k]
             if hits[i]:
-                need.add(j)
-            if hits[j]:
+                need.add(jj)
+            if hits[jj]:
                 need.add(i)
 
         def body(x, a=a, hits=hits, need=need):
-            if staged:
-                out = [f"const R w{c} = {v};" for c, v in zip(sorted(need), x)]
-            else:
-                out = [f"const R w{c} = {rowsM[c].format(*x)};" for c in sorted(need)]
+            out = [f"const R w{c} = {v};" for c, v in zip(sorted(need), x)]
             for k in range(3):
-                i, j = CYC[k]
-                for b in hits[i]:
-                    out.append(_fma(f"acc{k}_{b}", t.D[i][b, a], f"w{j}"))
-                for b in hits[j]:
-                    out.append(_fma(f"acc{k}_{b}", -t.D[j][b, a], f"w{i}"))
+                i, jj = CYC[k]
+                for j, b in hits[i]:
+                    out.append(_fma(f"acc{k}_{j}", t.D[i][b, a], f"w{jj}"))
+                for j, b in hits[jj]:
+                    out.append(_fma(f"acc{k}_{j}", -t.D[jj][b, a], f"w{i}"))
             return out
 
-        if staged:
-            blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in sorted(need)], body))
-        else:
-            blocks.append(([f"U[o + ({a}) * Ks + el]", f"U[o + ({N + a}) * Ks + el]", f"U[o + ({2 * N + a}) * Ks + el]"], body))
+        blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in sorted(need)], body))
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
-    jd = lambda f, k, m: f"jmp[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
-    lblocks = []
-    scalar_faces = []
+    a_(ind + "}")
+
+
+def _lift_job(a_, t, Lp, rows, ind):
+    """Lifted jumps (from LDS) added to the rates of the wave's rows, face by face,
+    then the update V = V_old + sdt * rate of the three components (old values
+    fetched before the lift arithmetic when the registers allow)."""
+    N, NF = t.N, t.NF
+    a_(ind + "{")
+    early = 6 * len(rows) <= VO_EARLY_MAX
+    if early:
+        a_(ind + "  // old values of the updated rows")
+        for j, b in enumerate(rows):
+            a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = V[({k * N + b}) * Ks + el]" for k in range(3)) + ";")
+    jd = lambda f, k, m: f"wl[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
     for f in range(4):
         ks = [k for k in range(3) if np.any(Lp[f][k] != 0)]
         ms = [m for m in range(NF) if np.any(t.T[f][m, rows] != 0)]
         if not ks or not ms:
             continue
         per_scalar = _lift_per_scalar(t, f, rows, Lp)
-        if per_scalar:
-            scalar_faces.append((f, ks))
+        lblocks = []
         for m in ms:
             def body(x, f=f, m=m, ks=ks, per_scalar=per_scalar):
                 out = []
-                for b in rows:
+                for j, b in enumerate(rows):
                     c = t.T[f][m, b]
                     if c == 0:
                         continue
                     if per_scalar:
-                        out.append(_fma(f"l{f}0_{b}", c, x[0]))
-                        out.append(_fma(f"l{f}1_{b}", c, x[1]))
+                        out.append(_fma(f"l0_{j}", c, x[0]))
+                        out.append(_fma(f"l1_{j}", c, x[1]))
                 for k in ks if not per_scalar else []:
                     c0, c1 = Lp[f][k]
                     terms = []
@@ -437,51 +347,51 @@ def _output_job(a_, t, Lp, rows, ind, staged=False):
                     if c1 != 0.0:
                         terms.append(f"{_lit(c1)} * {x[1]}")
                     out.append(f"const R g{k} = {' + '.join(terms)};")
-                    for b in rows:
+                    for j, b in enumerate(rows):
                         c = t.T[f][m, b]
                         if c != 0:
-                            out.append(_fma(f"acc{k}_{b}", c, f"g{k}"))
+                            out.append(_fma(f"acc{k}_{j}", c, f"g{k}"))
                 return out
             lblocks.append(([jd(f, 0, m), jd(f, 1, m)], body))
-    for f, ks in scalar_faces:
-        used = [b for b in rows if np.any(t.T[f][:, b] != 0)]
-        a_(ind + "  R " + ", ".join(f"l{f}{k}_{b} = R(0)" for b in used for k in range(2)) + ";")
-    a_(ind + "  {")
-    _Stream(a_, ind + "    ", "pj").emit(lblocks)
-    a_(ind + "  }")
-    for f, ks in scalar_faces:
-        for b in rows:
-            if not np.any(t.T[f][:, b] != 0):
-                continue
-            for k in ks:
-                c0, c1 = Lp[f][k]
-                if c0 != 0.0:
-                    a_(ind + "  " + _fma(f"acc{k}_{b}", c0, f"l{f}0_{b}"))
-                if c1 != 0.0:
-                    a_(ind + "  " + _fma(f"acc{k}_{b}", c1, f"l{f}1_{b}"))
+        a_(ind + f"  {{  // face {f}")
+        used = [j for j, b in enumerate(rows) if np.any(t.T[f][:, b] != 0)]
+        if per_scalar:
+            a_(ind + "    R " + ", ".join(f"l{k}_{j} = R(0)" for j in used for k in range(2)) + ";")
+        a_(ind + "    {")
+        _Stream(a_, ind + "      ", "pj").emit(lblocks)
+        a_(ind + "    }")
+        if per_scalar:
+            for j in used:
+                for k in ks:
+                    c0, c1 = Lp[f][k]
+                    if c0 != 0.0:
+                        a_(ind + "    " + _fma(f"acc{k}_{j}", c0, f"l0_{j}"))
+                    if c1 != 0.0:
+                        a_(ind + "    " + _fma(f"acc{k}_{j}", c1, f"l1_{j}"))
+        a_(ind + "  }")
     a_(ind + "  if (act) {")
-    for b in rows:
+    for j, b in enumerate(rows):
         for k in range(3):
-            a_(ind + f"    V[({k * N + b}) * Ks + e] = vo{k}_{b} + sdt * acc{k}_{b};")
+            old = f"vo{k}_{j}" if early else f"V[({k * N + b}) * Ks + e]"
+            a_(ind + f"    V[({k * N + b}) * Ks + e] = {old} + sdt * acc{k}_{j};")
     a_(ind + "  }")
     a_(ind + "}")
 
 
-def _lds_floats(t, staged):
-    """LDS words of one workgroup: the staged field (3N x 64) and the area shared by
-    the jumps (8NF x 64) and the element-major trace staging (64 x (ES + 1))."""
-    _, ES = trace_strides(t.NF)
-    jm = max(8 * t.NF * LANES, LANES * (ES + 1))
-    return (3 * t.N * LANES if staged else 0) + jm, jm
-
-
-def staged_fits(p: int, elem_bytes: int = 4) -> bool:
-    """Whether a tile's own field and the jump/trace area fit in the LDS budget."""
-    return _lds_floats(TB.build(p), True)[0] * elem_bytes <= LDS_BUDGET
+def lds_words(p: int) -> int:
+    """LDS words of one workgroup: one area, holding in turn the staged field
+    (3N x 64) and the trace jumps (8NF x 64)."""
+    t = TB.build(p)
+    return max(3 * t.N, 8 * t.NF) * LANES
 
 
 def waves_for(p: int) -> int:
     return 8 if p >= 4 else 4
+
+
+def groups_per_cu(p: int, elem_bytes: int) -> int:
+    """Workgroups that share a compute unit (LDS bound, at most 2)."""
+    return max(1, min(2, LDS_BUDGET // (lds_words(p) * elem_bytes)))
 
 
 def _stage_parts(t, nw, X, mp):
@@ -491,17 +401,21 @@ def _stage_parts(t, nw, X, mp):
     index is clamped, so a wave past the end rewrites mode N - 1 with the same values."""
     N = t.N
     cnt = -(-N // nw)
-    ld = [f"const R n00 = {mp}[0 * Ks + el], n01 = {mp}[1 * Ks + el], n02 = {mp}[2 * Ks + el];",
-          f"const R n11 = {mp}[3 * Ks + el], n12 = {mp}[4 * Ks + el], n22 = {mp}[5 * Ks + el];"]
+    # an opaque copy of the element index keeps the compiler from sharing this
+    # stage's address arithmetic with another stage (which would hold it in
+    # registers across the barriers in between)
+    ld = ["int ez = el, lz = lane;", "asm volatile(\"\" : \"+v\"(ez), \"+v\"(lz));",
+          f"const R n00 = {mp}[0 * Ks + ez], n01 = {mp}[1 * Ks + ez], n02 = {mp}[2 * Ks + ez];",
+          f"const R n11 = {mp}[3 * Ks + ez], n12 = {mp}[4 * Ks + ez], n22 = {mp}[5 * Ks + ez];"]
     st = []
     for i in range(cnt):
         idx = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {N - 1})"
         ld.append(f"const int a{i} = {idx};")
-        ld.append(f"const R s{i}_0 = {X}[(size_t)a{i} * Ks + el], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + el], "
-                  f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + el];")
-        st.append(f"wl[a{i} * {LANES} + lane] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
-        st.append(f"wl[({N} + a{i}) * {LANES} + lane] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
-        st.append(f"wl[({2 * N} + a{i}) * {LANES} + lane] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
+        ld.append(f"const R s{i}_0 = {X}[(size_t)a{i} * Ks + ez], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + ez], "
+                  f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + ez];")
+        st.append(f"wl[a{i} * {LANES} + lz] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
+        st.append(f"wl[({N} + a{i}) * {LANES} + lz] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
+        st.append(f"wl[({2 * N} + a{i}) * {LANES} + lz] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
     return ld, st
 
 
@@ -513,119 +427,113 @@ def _stage_field(a_, t, nw, X, mp):
     a_("  }")
 
 
-def _load_m(a_, mp, reg):
-    a_(f"  const R {reg}00 = {mp}[0 * Ks + el], {reg}01 = {mp}[1 * Ks + el], {reg}02 = {mp}[2 * Ks + el];")
-    a_(f"  const R {reg}11 = {mp}[3 * Ks + el], {reg}12 = {mp}[4 * Ks + el], {reg}22 = {mp}[5 * Ks + el];")
+JUMP_BATCH = 4    # trace chunks per lane loaded before their LDS stores
 
 
-def _jump_parts(t, nw):
-    """Jumps of the tangential traces of U, read from its trace buffer Tin: neighbour
-    minus own on interior faces, (wall - 1) times own on walls.  Per face 2 NF
-    contiguous values of the own and of the neighbour's face block, four per 16-byte
-    load.  Wave w takes chunks w, w + nw, ...  Returns (codes, loads, stores): the
-    neighbour codes, then every trace load (on walls the 'neighbour' load re-reads the
-    own block), then the LDS stores.  The last chunk index is clamped; a wave past the
+def _jump_lines(t, nw):
+    """Jumps of the tangential traces of U, read from its trace buffer Tin into LDS:
+    neighbour minus own on interior faces, (wall - 1) times own on walls; per lane
+    and chunk one 16-byte load of the own and one of the neighbour's face block.
+    Wave w takes chunks w, w + nw, ...; in rounds of JUMP_BATCH chunks the codes are
+    loaded first, then the trace values (on walls the 'neighbour' load re-reads the
+    own chunk), then the stores.  The last chunk index is clamped; a wave past the
     end rewrites the last chunk with the same values."""
     NF = t.NF
     FS, ES = trace_strides(NF)
     FQ = FS // 4
     cnt = -(-4 * FQ // nw)
-    codes, loads, stores = [], [], []
-    for i in range(cnt):
-        q = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {4 * FQ - 1})"
-        codes.append(f"const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
-        codes.append(f"const int code{i} = nbr[f{i} * Ks + el];")
-    for i in range(cnt):
-        loads.append(f"const size_t src{i} = code{i} >= 0 ? (size_t)(code{i} >> 2) * {ES} + (code{i} & 3) * {FS} + c{i} "
-                     f": (size_t)el * {ES} + f{i} * {FS} + c{i};")
-        loads.append(f"const R* so{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)el * {ES} + f{i} * {FS} + c{i}, 16);")
-        loads.append(f"const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + src{i}, 16);")
-        loads.append(f"const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
-        loads.append(f"const R t{i}_0 = sn{i}[0], t{i}_1 = sn{i}[1], t{i}_2 = sn{i}[2], t{i}_3 = sn{i}[3];")
-    stores.append("const R cw = wall - R(1);")
-    for i in range(cnt):
-        stores.append(f"{{")
-        stores.append(f"  const bool in = code{i} >= 0;")
-        stores.append(f"  R* d = jmp + (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
-        for j in range(4):
-            st = f"d[{j * LANES}] = in ? t{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
-            stores.append(f"  {st}" if j == 0 else f"  if (c{i} + {j} < {2 * NF}) {st}")
-        stores.append(f"}}")
-    return codes, loads, stores
+    L = [f"const size_t own = (size_t)(el >> 6) * {LANES * ES} + (size_t)(el & 63) * 4;",
+         "const R cw = wall - R(1);"]
+    for r0 in range(0, cnt, JUMP_BATCH):
+        idx = range(r0, min(cnt, r0 + JUMP_BATCH))
+        L.append("{")
+        for i in idx:
+            q = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {4 * FQ - 1})"
+            L.append(f"  const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
+            L.append(f"  const int code{i} = nbr[f{i} * Ks + el];")
+        for i in idx:
+            L.append(f"  const int nb{i} = code{i} >= 0 ? code{i} >> 2 : el;")
+            L.append(f"  const int gf{i} = code{i} >= 0 ? code{i} & 3 : f{i};")
+            L.append(f"  const R* so{i} = (const R*)__builtin_assume_aligned(Tin + own + (size_t)q{i} * {LANES * 4}, 16);")
+            L.append(f"  const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)(nb{i} >> 6) * {LANES * ES} "
+                     f"+ ((size_t)(gf{i} * {FQ} + (q{i} - f{i} * {FQ})) * {LANES} + (nb{i} & 63)) * 4, 16);")
+            L.append(f"  const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
+            L.append(f"  const R t{i}_0 = sn{i}[0], t{i}_1 = sn{i}[1], t{i}_2 = sn{i}[2], t{i}_3 = sn{i}[3];")
+        for i in idx:
+            L.append("  {")
+            L.append(f"    const bool in = code{i} >= 0;")
+            L.append(f"    const int d = (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
+            for j in range(4):
+                st = f"wl[d + {j * LANES}] = in ? t{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
+                L.append(f"    {st}" if j == 0 else f"    if (c{i} + {j} < {2 * NF}) {st}")
+            L.append("  }")
+        L.append("}")
+    return L
 
 
-def _trace_stage(a_, t, g, pl, nw, src):
-    """Own traces of one field into the staging area, then one coalesced copy of the
-    tile's contiguous block (64 elements x ES values) to the trace buffer."""
-    NF = t.NF
-    FS, ES = trace_strides(NF)
+def _trace_stage(a_, t, g, pl, nw):
+    """Trace jobs of the field staged in LDS, stored straight to the tile's block."""
+    a_(f"  const size_t tb = (size_t)tile * {LANES * trace_strides(t.NF)[1]};")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for (f, rows) in pl["trace"][w]:
             a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ", src)
+            _trace_job(a_, t, g, f, rows, "    ")
         a_("  }")
-    a_("  __syncthreads();")
-    a_("  {")
-    a_(f"    const int nel = K - tile * {LANES} < {LANES} ? K - tile * {LANES} : {LANES};")
-    a_(f"    R* __restrict__ dst = Tout + (size_t)tile * {LANES * ES};")
-    a_(f"    for (int i = threadIdx.x; i < nel * {ES}; i += {nw * LANES}) {{")
-    a_(f"      const int q = i / {ES}, c = i - q * {ES};")
-    a_(f"      dst[i] = (c % {FS}) < {2 * NF} ? jmp[q * {ES + 1} + c] : R(0);")
-    a_("    }")
-    a_("  }")
 
 
-def _phase_body(a_, t, g, Lp, pl, nw, staged):
-    """Stages of one phase (shared by the single-mesh and the batched kernel):
-    1 stage U (derivative frame) and form the trace jumps from the trace buffer,
-    2 curl + lift + update of V, 3 (if Tout) traces of the new V."""
-    codes, tl, ts = _jump_parts(t, nw)
-    if staged:
-        sl, ss = _stage_parts(t, nw, "U", "MU")
-    else:
-        _load_m(a_, "MU", "m")
-        sl, ss = [], []
-    a_("  // stage 1: the tile's own field in the derivative frame, w = M S, into LDS, and the")
-    a_("  // jumps of the traces of U (own and neighbour face blocks of its trace buffer);")
-    a_("  // neighbour codes first, then the field and trace loads, then the LDS stores")
-    a_("  {")
-    for l in codes + sl + tl + ss + ts:
-        a_("    " + l)
-    a_("  }")
+def _phase_body(a_, t, g, Lp, pl, nw):
+    """Stages of one phase (shared by the single-mesh and the batched kernel), one
+    LDS area used in turn: A stage U (derivative frame), B curl of the wave's rows
+    into registers, C jumps of the traces of U, D lift + update of V, and if Tout:
+    E stage the updated V, F its traces to Tout."""
+    J = max(len(rows) for w in pl["out"] for rows in w) if any(pl["out"]) else 0
+    for k in range(3):
+        for j0 in range(0, J, 16):
+            a_("  R " + ", ".join(f"acc{k}_{j} = R(0)" for j in range(j0, min(J, j0 + 16))) + ";")
+    a_("  // A: the tile's own field in the derivative frame, w = M S, into LDS")
+    _stage_field(a_, t, nw, "U", "MU")
     a_("  __syncthreads();")
-    a_("  // stage 2: curl and lifted jumps, component-separable update")
+    a_("  // B: curl of the wave's rows (all components) into registers")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for rows in pl["out"][w]:
-            a_(f"    // volume modes {rows[0]}..{rows[-1]}, all components")
-            _output_job(a_, t, Lp, rows, "    ", staged)
+            a_(f"    // volume modes {', '.join(map(str, rows))}")
+            _curl_job(a_, t, rows, "    ")
+        a_("  }")
+    a_("  __syncthreads();")
+    a_("  // C: jumps of the traces of U (own and neighbour chunks of its trace buffer)")
+    a_("  {")
+    for l in _jump_lines(t, nw):
+        a_("    " + l)
+    a_("  }")
+    a_("  __syncthreads();")
+    a_("  // D: lifted jumps and the component-separable update of V")
+    for w in range(nw):
+        a_(f"  if (wave == {w}) {{")
+        for rows in pl["out"][w]:
+            _lift_job(a_, t, Lp, rows, "    ")
         a_("  }")
     a_("  if (Tout == nullptr) return;")
-    a_("  // stage 3: traces of the updated field for the next phase (V re-read from L2)")
+    a_("  // E: the updated field (re-read from L2) in the derivative frame into LDS")
     a_("  __syncthreads();")
-    if staged:
-        _stage_field(a_, t, nw, "V", "MV")
-        a_("  __syncthreads();")
-        _trace_stage(a_, t, g, pl, nw, "lds")
-    else:
-        _load_m(a_, "MV", "mv")
-        _trace_stage(a_, t, g, pl, nw, ("V", "mv"))
+    _stage_field(a_, t, nw, "V", "MV")
+    a_("  __syncthreads();")
+    a_("  // F: its traces for the next phase")
+    _trace_stage(a_, t, g, pl, nw)
 
 
 def _kernel_setup(p):
     t = TB.build(p)
     g, Lp = TB.face_weights(t)
     nw = waves_for(p)
-    staged = staged_fits(p, 4) and (p > F64_MAX_ORDER or staged_fits(p, 8))
-    return t, g, Lp, nw, staged, plan(p, nw)
+    return t, g, Lp, nw, plan(p, nw)
 
 
-def _lds_decl(a_, t, staged):
-    tot, jm = _lds_floats(t, staged)
-    a_(f"  __shared__ R jmp[{jm}];")
-    if staged:
-        a_(f"  __shared__ R wl[{3 * t.N * LANES}];")
+def _launch_bounds(p, nw):
+    """Threads per workgroup and minimum waves per SIMD (from the LDS-bound number
+    of workgroups per CU at FP32), which caps the registers per lane."""
+    return f"__launch_bounds__({nw * LANES}, {max(1, nw * groups_per_cu(p, 4) // 4)})"
 
 
 def _tile_prologue(a_):
@@ -645,73 +553,69 @@ def _elem_prologue(a_):
     a_("  const size_t Ks = (size_t)K;")
 
 
-def _header(a_, p, t, nw, staged, pl, what):
+def _header(a_, p, t, nw, pl, what):
     FS, ES = trace_strides(t.NF)
     a_(f"// Generated by gen/emit.py for order p = {p}: N = {t.N} volume modes, NF = {t.NF} face modes; {what}.")
-    a_(f"// {nw} waves share {LANES} elements (one per lane); own field staged in LDS: {staged};")
-    a_(f"// trace buffer strides: face {FS}, element {ES}; trace cost per wave {pl['trace_load']},")
-    a_(f"// output cost per wave {pl['out_load']}.")
+    a_(f"// {nw} waves share {LANES} elements (one per lane), {lds_words(p)} LDS words; trace buffer")
+    a_(f"// strides: face {FS}, element {ES}; per-wave cost of the trace jobs {pl['trace_load']},")
+    a_(f"// of the update jobs {pl['out_load']}.")
     a_(f"static_assert(trace_face_stride({t.NF}) == {FS} && trace_elem_stride({t.NF}) == {ES}, \"trace layout\");")
 
 
 def emit_phase(p: int) -> str:
     """Single-mesh phase kernel of order p."""
-    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    t, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
-    _header(a_, p, t, nw, staged, pl, "single-mesh phase")
+    _header(a_, p, t, nw, pl, "single-mesh phase")
     a_("template <typename R>")
-    a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
+    a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
     a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K)")
     a_("{")
-    _lds_decl(a_, t, staged)
+    a_(f"  __shared__ R wl[{lds_words(p)}];")
     _tile_prologue(a_)
     _elem_prologue(a_)
-    _phase_body(a_, t, g, Lp, pl, nw, staged)
+    _phase_body(a_, t, g, Lp, pl, nw)
     a_("}")
     return "\n".join(L) + "\n"
 
 
 def emit_trace(p: int) -> str:
-    """Trace kernel of order p: element-major traces of one field (the first phase
-    of a run and the rate operator need them before any phase has written them)."""
-    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    """Trace kernel of order p: the traces of one field (the first phase of a run
+    and the rate operator need them before any phase has written them)."""
+    t, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
-    _header(a_, p, t, nw, staged, pl, "trace kernel")
+    _header(a_, p, t, nw, pl, "trace kernel")
     a_("template <typename R>")
-    a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_trace_p{p}(const R* __restrict__ U,")
+    a_(f"__global__ void {_launch_bounds(p, nw)} dgm_trace_p{p}(const R* __restrict__ U,")
     a_("    const R* __restrict__ MU, R* __restrict__ Tout, int K)")
     a_("{")
-    _lds_decl(a_, t, staged)
+    a_(f"  __shared__ R wl[{lds_words(p)}];")
     _tile_prologue(a_)
     _elem_prologue(a_)
-    if staged:
-        _stage_field(a_, t, nw, "U", "MU")
-        a_("  __syncthreads();")
-        _trace_stage(a_, t, g, pl, nw, "lds")
-    else:
-        _load_m(a_, "MU", "m")
-        _trace_stage(a_, t, g, pl, nw, ("U", "m"))
+    _stage_field(a_, t, nw, "U", "MU")
+    a_("  __syncthreads();")
+    _trace_stage(a_, t, g, pl, nw)
     a_("}")
     return "\n".join(L) + "\n"
 
 
 def emit_batch(p: int) -> str:
     """Batched multi-mesh phase kernel of order p (FP32)."""
-    t, g, Lp, nw, staged, pl = _kernel_setup(p)
+    t, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
-    _header(a_, p, t, nw, staged, pl, "batched phase")
+    _header(a_, p, t, nw, pl, "batched phase")
     a_("// One launch advances every slot (mesh) of this order.  Block b belongs to the last")
     a_("// slot s with tile0[s] <= b; blocks past the table, or of slots whose remaining")
     a_("// steps are exhausted at this sub-step, exit before any barrier.")
     a_("template <typename R>")
-    a_(f"__global__ void __launch_bounds__({nw * LANES}) dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
+    a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
     a_("    const int* __restrict__ tile0, const int* __restrict__ nslots, int phase, int substep)")
     a_("{")
-    _lds_decl(a_, t, staged)
+    a_(f"  __shared__ R wl[{lds_words(p)}];")
     a_("  const int nsl = *nslots;")
     a_("  const int bid = blockIdx.x;")
     a_("  if (nsl <= 0 || bid >= tile0[nsl]) return;")
@@ -731,7 +635,7 @@ def emit_batch(p: int) -> str:
     a_("  const int K = sl.K;")
     a_("  const int tile = bid - tile0[lo];")
     _elem_prologue(a_)
-    _phase_body(a_, t, g, Lp, pl, nw, staged)
+    _phase_body(a_, t, g, Lp, pl, nw)
     a_("}")
     return "\n".join(L) + "\n"
 
