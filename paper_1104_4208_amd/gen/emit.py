@@ -49,7 +49,7 @@ def _fma(acc, coef, x):
 
 LANES = 64
 LDS_BUDGET = 160 * 1024  # bytes of LDS per compute unit
-F64_MAX_ORDER = 4   # highest order also instantiated in FP64 (compile time grows steeply with p)
+F64_MAX_ORDER = 6   # highest order also instantiated in FP64 (the staged field, 3N x 64 doubles, must fit in LDS)
 
 
 TRACE_ROWS = 32   # face modes per trace job (bounds the job's accumulators)
@@ -655,6 +655,8 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     units = []
     for p in orders:
         nw = waves_for(p)
+        assert lds_words(p) * 4 <= LDS_BUDGET, f"order {p}: LDS area too large"
+        assert p > F64_MAX_ORDER or lds_words(p) * 8 <= LDS_BUDGET, f"order {p}: FP64 LDS area too large"
         _write_if_changed(os.path.join(outdir, f"phase_p{p}.inc"), emit_phase(p))
         _write_if_changed(os.path.join(outdir, f"batch_p{p}.inc"), emit_batch(p))
         tu = [f"// Generated by gen/emit.py: instantiation and launcher for order {p}.",
