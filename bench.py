@@ -40,6 +40,21 @@ WORKLOAD = dict(workload="pec_cube_cavity_kuhn32_p6_fp32", cells=32, tets=196608
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_p6_cube32_traffic.json")
 
 
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the
+    generated p = 6 kernel source differs from the one the counters were taken on."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1104_4208_amd", "csrc", "generated", "phase_p6.inc")
+    if not (os.path.exists(TRAFFIC_FILE) and os.path.exists(src)):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        tr = json.load(fh)
+    with open(src, "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return tr.get("bytes_per_launch") if tr.get("kernel_source_sha256_16") == h else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,11 +239,7 @@ def main():
     bytes_launch = K * (36 * N + 40)
     achieved = bytes_launch / phase_s / 1e9
     value = 6 * N * K * a.steps / wall
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        traffic = tr.get("bytes_per_launch")
+    traffic = measured_traffic()
     out = {
         "metric": "DOF-updates/sec & %HBM roofline at p=6 (FP32 vs FP64 oracle err); serving p50/p99",
         "value": value,
