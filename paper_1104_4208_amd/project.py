@@ -8,6 +8,9 @@ F is built from the element's vertices sorted by global id, as in the library.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
+import os
+
 import numpy as np
 
 from .gen import basis as B
@@ -29,12 +32,22 @@ def project_covariant(verts, tets, p: int, fn, chunk: int = 4096) -> np.ndarray:
     V = B.volume_values(p, xq)
     K = F.shape[0]
     out = np.empty((3, V.shape[0], K))
-    for s in range(0, K, chunk):
+    W = np.ascontiguousarray((V * wq[None, :]).T)  # (Q, N) quadrature weights times basis values
+
+    def part(s):
         sl = slice(s, min(s + chunk, K))
-        x = v0[sl, None, :] + np.einsum("kij,qj->kqi", F[sl], xq)
+        x = v0[sl, None, :] + sum(xq[None, :, j, None] * F[sl, None, :, j] for j in range(3))
         f = fn(x)
-        mom = np.einsum("mq,kqd->kmd", V * wq[None, :], f)  # int f phi_m over the reference tet
-        out[:, :, sl] = np.einsum("kji,kmj->imk", F[sl], mom)  # F^T applied per mode
+        mom = np.matmul(f.transpose(0, 2, 1), W)  # (k, 3, N): int f phi_m over the reference tet
+        out[:, :, sl] = np.matmul(F[sl].transpose(0, 2, 1), mom).transpose(1, 2, 0)  # F^T per mode
+
+    starts = list(range(0, K, chunk))
+    if len(starts) > 1:
+        # numpy releases the GIL in its ufuncs and matrix products: chunks run in parallel
+        with cf.ThreadPoolExecutor(max_workers=min(len(starts), os.cpu_count() or 1, 16)) as ex:
+            list(ex.map(part, starts))
+    else:
+        part(0)
     return out
 
 

@@ -64,7 +64,7 @@ class Request:
 
 
 def make_trace(num=256, rate=50.0, seed=5, n_range=(4, 24), p_range=(2, 8), eps_choices=(1.0, 2.0, 4.0),
-               steps_range=(200, 2000), jitter=0.1, dt_cfl=0.5):
+               steps_range=(200, 2000), jitter=0.1, dt_cfl=0.5, progress=False):
     """Poisson arrivals (mean rate per second) of cavity solves, drawn in the fixed
     order: per request n, p, eps, steps, then the mesh jitter; arrival gaps last."""
     import synth
@@ -82,6 +82,8 @@ def make_trace(num=256, rate=50.0, seed=5, n_range=(4, 24), p_range=(2, 8), eps_
     arrivals = np.cumsum(gaps) - gaps[0]
     reqs = []
     for r, ((n, p, eps, steps, verts, tets), t) in enumerate(zip(specs, arrivals)):
+        if progress and r % 16 == 0:
+            print(f"[serve] preparing request {r}/{num}", file=sys.stderr, flush=True)
         mode = synth.te101(eps=eps)
         E0 = project_covariant(verts, tets, p, mode.E).astype(np.float32)
         # dt from the stability bound of this mesh (power iteration, 20 steps)
@@ -194,13 +196,18 @@ def closed_form_error(req, E, H):
     return math.sqrt(num / den)
 
 
-def serve_report(num=256, budget_gib=2.0, chunk=20, n_range=(4, 24), steps_range=(200, 2000), check=8):
+def serve_report(num=256, budget_gib=2.0, chunk=20, n_range=(4, 24), steps_range=(200, 2000), check=8,
+                 progress=False):
     """Batched and sequential runs of the same trace, plus the alone-vs-mix check on
     `check` requests and their closed-form errors."""
-    trace = make_trace(num=num, n_range=n_range, steps_range=steps_range)
+    trace = make_trace(num=num, n_range=n_range, steps_range=steps_range, progress=progress)
     srv = Server(int(budget_gib * 2 ** 30), chunk)
     ids = set(range(min(check, num)))
+    if progress:
+        print("[serve] batched run", file=sys.stderr, flush=True)
     rb, sb = srv.run(trace, "batched", keep_states=ids)
+    if progress:
+        print("[serve] sequential run", file=sys.stderr, flush=True)
     rs, ss = srv.run(trace, "sequential", keep_states=ids)
     diffs, errs = [], []
     for rid in sorted(ids):
@@ -226,7 +233,7 @@ def main():
     ap.add_argument("--nmax", type=int, default=24)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    rep = serve_report(a.requests, a.budget_gib, a.chunk, n_range=(4, a.nmax))
+    rep = serve_report(a.requests, a.budget_gib, a.chunk, n_range=(4, a.nmax), progress=True)
     line = json.dumps(rep)
     print(line, flush=True)
     if a.out:
