@@ -71,6 +71,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise DGMError(f"{path} is missing: build it with `python -m paper_1104_4208_amd.build`")
+    # torch ships its own HIP runtime with the same soname as the system one; importing
+    # it first makes the loader bind the library to that copy, so the process has one
+    # HIP runtime (two of them do not see the same devices)
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
