@@ -59,8 +59,11 @@ class Request:
         return self.dofs * self.steps
 
     def device_bytes(self):
-        """State (E, H FP32) plus the per-element geometry the library keeps."""
-        return 2 * 3 * D.num_modes(self.p) * self.K * 4 + self.K * 260
+        """State (E, H FP32), the two trace buffers and the per-element geometry the
+        library keeps for the mesh handle."""
+        nf = D.num_face_modes(self.p)
+        trace = ((self.K + 63) // 64) * 64 * 4 * ((2 * nf + 3) // 4 * 4)
+        return 2 * 3 * D.num_modes(self.p) * self.K * 4 + 2 * trace * 4 + self.K * 260
 
 
 def make_trace(num=256, rate=50.0, seed=5, n_range=(4, 24), p_range=(2, 8), eps_choices=(1.0, 2.0, 4.0),
