@@ -3,12 +3,21 @@
 #include <hip/hip_runtime.h>
 
 // Trace buffer of one field: per element four faces, each holding the two tangential
-// traces on the NF face modes (tangent major) padded to a multiple of four values.
+// traces on the NF face modes (tangent major), each tangent padded to a multiple of four.
 // Tiles of 64 elements are contiguous; inside a tile, chunk j (four consecutive
 // values of one face) of lane l sits at (j * 64 + l) * 4, so a workgroup stores its
 // traces coalesced and a neighbour's chunk is one 16-byte load.
-constexpr int trace_face_stride(int NF) { return (2 * NF + 3) & ~3; }
+constexpr int trace_face_stride(int NF) { return 2 * ((NF + 3) & ~3); }
 constexpr int trace_elem_stride(int NF) { return 4 * trace_face_stride(NF); }
+
+// One 16-byte-aligned chunk of four values (a lane's part of a coalesced store).
+__device__ inline void store4(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+__device__ inline void store4(double* p, double a, double b, double c, double d) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
+  reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+}
 
 template <typename R>
 struct PhaseArgs {

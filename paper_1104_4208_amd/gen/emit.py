@@ -209,12 +209,16 @@ def plan(p: int, nw: int):
             by_f[f] = by_f.get(f, 0) + 1
         return max(by_f.values()) <= TRACE_ROWS
 
-    tr_items = [(f, m) for f in range(4) for m in range(NF) if np.any(t.T[f][m] != 0)]
-    tb, tr_load = _balance(tr_items, lambda x: tr_bin([x]), tr_bin, nw, tr_cap)
+    # items: quads of four face modes (one 16-byte store per tangent)
+    quads = lambda f, q: [(f, m) for m in range(4 * q, min(NF, 4 * q + 4))]
+    tr_items = [(f, q) for f in range(4) for q in range((NF + 3) // 4)]
+    expand = lambda items: [fm for f, q in items for fm in quads(f, q)]
+    tb, tr_load = _balance(tr_items, lambda x: tr_bin(expand([x])), lambda it: tr_bin(expand(it)), nw,
+                           lambda it: tr_cap(expand(it)))
     tr_w = []
     for items in tb:
         by_f = {}
-        for f, m in items:
+        for f, m in expand(items):
             by_f.setdefault(f, []).append(m)
         tr_w.append([(f, sorted(ms)) for f, ms in sorted(by_f.items())])
     ob, out_load = _balance(list(range(N)), lambda b: _out_job_cost(t, Lp, [b]),
@@ -224,26 +228,24 @@ def plan(p: int, nw: int):
 
 
 def trace_strides(NF: int):
-    """Trace buffer of one field: per element four faces of FS values (the 2 NF
-    traces, tangent major, padded to a multiple of four), ES = 4 FS per element.
-    Tile-blocked and quad-interleaved: for the 64 elements of a tile, the four
-    values of chunk q (= face f, values 4j..4j+3) of lane l sit at
-    ((f FQ + j) 64 + l) 4, so a tile's threads store coalesced and a neighbour's
-    chunk is one 16-byte load."""
-    FS = (2 * NF + 3) & ~3
+    """Trace buffer of one field: per element four faces of FS values (tangent 1,
+    then tangent 2, each over the NF face modes padded to NFP, a multiple of four),
+    ES = 4 FS per element.  Tile-blocked and quad-interleaved: for the 64 elements
+    of a tile, the four values of chunk q (face f, values 4j..4j+3 of the face) of
+    lane l sit at ((f FQ + j) 64 + l) 4, so a tile's threads store coalesced and a
+    neighbour's chunk is one 16-byte load; a chunk never spans both tangents."""
+    NFP = (NF + 3) & ~3
+    FS = 2 * NFP
     return FS, 4 * FS
 
 
-def _trace_index(NF, f, c, lane="lane"):
-    FS, ES = trace_strides(NF)
-    FQ = FS // 4
-    return f"(({f * FQ + c // 4}) * {LANES} + {lane}) * 4 + {c % 4}"
-
-
 def _trace_job(a_, t, g, f, rows, ind):
-    """Tangential traces tau_k = g_fk . w on face f, face rows `rows`, of the field
-    staged in LDS (derivative frame), stored to the tile's block of Tout."""
+    """Tangential traces tau_k = g_fk . w on face f, face rows `rows` (whole quads of
+    four face modes), of the field staged in LDS (derivative frame), stored to the
+    tile's block of Tout with one 16-byte store per lane, tangent and quad."""
     N, NF = t.N, t.NF
+    FS, ES = trace_strides(NF)
+    NFP, FQ = FS // 2, FS // 4
     a_(ind + "{")
     a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
     blocks = []
@@ -269,9 +271,11 @@ def _trace_job(a_, t, g, f, rows, ind):
     a_(ind + "  {")
     _Stream(a_, ind + "    ", "pf").emit(blocks)
     a_(ind + "  }")
-    for m in rows:
+    for mq in sorted({m // 4 for m in rows}):
         for k in range(2):
-            a_(ind + f"  Tout[tb + {_trace_index(NF, f, k * NF + m)}] = ts{k}_{m};")
+            vals = [f"ts{k}_{m}" if m in rows else "R(0)" for m in range(4 * mq, 4 * mq + 4)]
+            chunk = f * FQ + (k * NFP + 4 * mq) // 4
+            a_(ind + f"  store4(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
     a_(ind + "}")
 
 
@@ -440,7 +444,7 @@ def _jump_lines(t, nw):
     end rewrites the last chunk with the same values."""
     NF = t.NF
     FS, ES = trace_strides(NF)
-    FQ = FS // 4
+    NFP, FQ = FS // 2, FS // 4
     cnt = -(-4 * FQ // nw)
     L = [f"const size_t own = (size_t)(el >> 6) * {LANES * ES} + (size_t)(el & 63) * 4;",
          "const R cw = wall - R(1);"]
@@ -462,10 +466,11 @@ def _jump_lines(t, nw):
         for i in idx:
             L.append("  {")
             L.append(f"    const bool in = code{i} >= 0;")
-            L.append(f"    const int d = (f{i} * {2 * NF} + c{i}) * {LANES} + lane;")
+            L.append(f"    const int k = c{i} >= {NFP}, m = c{i} - k * {NFP};")
+            L.append(f"    const int d = ((f{i} * 2 + k) * {NF} + m) * {LANES} + lane;")
             for j in range(4):
                 st = f"wl[d + {j * LANES}] = in ? t{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
-                L.append(f"    {st}" if j == 0 else f"    if (c{i} + {j} < {2 * NF}) {st}")
+                L.append(f"    {st}" if (j == 0 and NF % 4 == 0) else f"    if (m + {j} < {NF}) {st}")
             L.append("  }")
         L.append("}")
     return L

@@ -62,7 +62,7 @@ class Request:
         """State (E, H FP32), the two trace buffers and the per-element geometry the
         library keeps for the mesh handle."""
         nf = D.num_face_modes(self.p)
-        trace = ((self.K + 63) // 64) * 64 * 4 * ((2 * nf + 3) // 4 * 4)
+        trace = ((self.K + 63) // 64) * 64 * 4 * 2 * ((nf + 3) // 4 * 4)
         return 2 * 3 * D.num_modes(self.p) * self.K * 4 + 2 * trace * 4 + self.K * 260
 
 
