@@ -188,6 +188,61 @@ def _balance(items, single, bin_cost, nw, cap, sweeps=4):
     return bins, load
 
 
+def _plan_traces(t, g, nw):
+    """Trace jobs: every face is cut into s_f contiguous runs of quads (four face
+    modes, one 16-byte store per tangent), the runs are spread over the waves
+    longest first, and the cut (s_0..s_3) with the smallest largest wave load is
+    kept (fewest jobs on ties).  Few jobs per face keep the re-streaming of the
+    staged field (LDS reads and frame conversions) low."""
+    import itertools
+
+    NF = t.NF
+    NQ = (NF + 3) // 4
+    rows_of = lambda i, j: list(range(4 * i, min(NF, 4 * j)))
+    cost = [[[0] * (NQ + 1) for _ in range(NQ + 1)] for _ in range(4)]
+    for f in range(4):
+        for i in range(NQ):
+            for j in range(i + 1, NQ + 1):
+                cost[f][i][j] = _trace_job_cost(t, g, f, rows_of(i, j)) if len(rows_of(i, j)) <= TRACE_ROWS else 10 ** 9
+
+    def cuts(f, s_f):
+        """Contiguous runs of face f's quads minimising the largest run cost (DP)."""
+        INF = 10 ** 18
+        best = [[INF] * (NQ + 1) for _ in range(s_f + 1)]
+        arg = [[0] * (NQ + 1) for _ in range(s_f + 1)]
+        best[0][0] = 0
+        for r in range(1, s_f + 1):
+            for j in range(1, NQ + 1):
+                for i in range(r - 1, j):
+                    v = max(best[r - 1][i], cost[f][i][j])
+                    if v < best[r][j]:
+                        best[r][j], arg[r][j] = v, i
+        out, j = [], NQ
+        for r in range(s_f, 0, -1):
+            i = arg[r][j]
+            out.append((i, j))
+            j = i
+        return out[::-1]
+
+    runs = {(f, s_f): cuts(f, s_f) for f in range(4) for s_f in range(1, min(nw, NQ) + 1)}
+    best = None
+    for split in itertools.product(range(1, min(nw, NQ) + 1), repeat=4):
+        if sum(split) > 2 * nw:
+            continue
+        jobs = [(cost[f][i][j], f, i, j) for f in range(4) for i, j in runs[(f, split[f])]]
+        load = [0] * nw
+        assign = [[] for _ in range(nw)]
+        for c, f, i, j in sorted(jobs, reverse=True):
+            w = min(range(nw), key=lambda w: load[w])
+            load[w] += c
+            assign[w].append((f, rows_of(i, j)))
+        key = (max(load), len(jobs))
+        if best is None or key < best[0]:
+            best = (key, assign, load)
+    _, assign, load = best
+    return [sorted(a) for a in assign], load
+
+
 def plan(p: int, nw: int):
     """One output job per wave (volume rows, all three components) and per wave one
     trace job per face it touches (face rows), balanced over the nw waves with the
@@ -197,30 +252,7 @@ def plan(p: int, nw: int):
     N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
 
-    def tr_bin(items):
-        by_f = {}
-        for f, m in items:
-            by_f.setdefault(f, []).append(m)
-        return sum(_trace_job_cost(t, g, f, sorted(ms)) for f, ms in by_f.items())
-
-    def tr_cap(items):
-        by_f = {}
-        for f, m in items:
-            by_f[f] = by_f.get(f, 0) + 1
-        return max(by_f.values()) <= TRACE_ROWS
-
-    # items: quads of four face modes (one 16-byte store per tangent)
-    quads = lambda f, q: [(f, m) for m in range(4 * q, min(NF, 4 * q + 4))]
-    tr_items = [(f, q) for f in range(4) for q in range((NF + 3) // 4)]
-    expand = lambda items: [fm for f, q in items for fm in quads(f, q)]
-    tb, tr_load = _balance(tr_items, lambda x: tr_bin(expand([x])), lambda it: tr_bin(expand(it)), nw,
-                           lambda it: tr_cap(expand(it)))
-    tr_w = []
-    for items in tb:
-        by_f = {}
-        for f, m in expand(items):
-            by_f.setdefault(f, []).append(m)
-        tr_w.append([(f, sorted(ms)) for f, ms in sorted(by_f.items())])
+    tr_w, tr_load = _plan_traces(t, g, nw)
     ob, out_load = _balance(list(range(N)), lambda b: _out_job_cost(t, Lp, [b]),
                             lambda rows: _out_job_cost(t, Lp, sorted(rows)), nw, lambda rows: len(rows) <= OUT_ROWS)
     out_w = [[sorted(rows)] if rows else [] for rows in ob]
