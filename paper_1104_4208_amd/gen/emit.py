@@ -56,8 +56,6 @@ TRACE_ROWS = 32   # face modes per trace job (bounds the job's accumulators)
 
 
 LDS_GROUP = 8     # mode blocks per basic block in a stream
-VO_EARLY_MAX = 96  # registers the old values plus rates of a wave's rows may hold
-                   # through the lift (else the old values are read at the update)
 
 
 class _Stream:
@@ -352,7 +350,7 @@ def _lift_job(a_, t, Lp, rows, ind):
     fetched before the lift arithmetic when the registers allow)."""
     N, NF = t.N, t.NF
     a_(ind + "{")
-    early = 6 * len(rows) <= VO_EARLY_MAX
+    early = vo_early(t.p)
     if early:
         a_(ind + "  // old values of the updated rows")
         for j, b in enumerate(rows):
@@ -421,8 +419,18 @@ def lds_words(p: int) -> int:
     return max(3 * t.N, 8 * t.NF) * LANES
 
 
+# Waves per workgroup and whether a wave fetches the old values of its rows before
+# the lift (else at the update), per order; chosen by timing the p = 6, 7, 8 phase
+# kernels on the 32^3 mesh (16 waves at p = 8 need the late fetch to avoid spills).
+LAUNCH = {8: (16, False)}
+
+
 def waves_for(p: int) -> int:
-    return 8 if p >= 4 else 4
+    return LAUNCH[p][0] if p in LAUNCH else (8 if p >= 4 else 4)
+
+
+def vo_early(p: int) -> bool:
+    return LAUNCH[p][1] if p in LAUNCH else True
 
 
 def groups_per_cu(p: int, elem_bytes: int) -> int:
