@@ -238,7 +238,24 @@ def _plan_traces(t, g, nw):
         if best is None or key < best[0]:
             best = (key, assign, load)
     _, assign, load = best
-    return [sorted(a) for a in assign], load
+    out = []
+    for w, jobs in enumerate(assign):
+        # two runs of one face on one wave: one stream if the accumulators allow
+        by_f = {}
+        for f, rows in jobs:
+            by_f.setdefault(f, []).append(rows)
+        merged = []
+        for f, runs_f in sorted(by_f.items()):
+            cur = []
+            for rows in sorted(runs_f):
+                if cur and len(cur) + len(rows) > TRACE_ROWS:
+                    merged.append((f, cur))
+                    cur = []
+                cur = sorted(cur + rows)
+            merged.append((f, cur))
+        out.append(merged)
+        load[w] = sum(_trace_job_cost(t, g, f, rows) for f, rows in merged)
+    return out, load
 
 
 def plan(p: int, nw: int):
@@ -403,11 +420,15 @@ def _lift_job(a_, t, Lp, rows, ind):
                     if c1 != 0.0:
                         a_(ind + "    " + _fma(f"acc{k}_{j}", c1, f"l1_{j}"))
         a_(ind + "  }")
+    # the new values stay in the accumulator slots (the traces of V are formed from them)
+    for j, b in enumerate(rows):
+        for k in range(3):
+            old = f"vo{k}_{j}" if early else f"V[({k * N + b}) * Ks + el]"
+            a_(ind + f"  acc{k}_{j} = {old} + sdt * acc{k}_{j};")
     a_(ind + "  if (act) {")
     for j, b in enumerate(rows):
         for k in range(3):
-            old = f"vo{k}_{j}" if early else f"V[({k * N + b}) * Ks + e]"
-            a_(ind + f"    V[({k * N + b}) * Ks + e] = {old} + sdt * acc{k}_{j};")
+            a_(ind + f"    V[({k * N + b}) * Ks + e] = acc{k}_{j};")
     a_(ind + "  }")
     a_(ind + "}")
 
@@ -531,7 +552,9 @@ def _phase_body(a_, t, g, Lp, pl, nw):
     """Stages of one phase (shared by the single-mesh and the batched kernel), one
     LDS area used in turn: A stage U (derivative frame), B curl of the wave's rows
     into registers, C jumps of the traces of U, D lift + update of V, and if Tout:
-    E stage the updated V, F its traces to Tout."""
+    E the updated rows (kept in registers) into LDS in the derivative frame of V,
+    F its traces to Tout."""
+    N = t.N
     J = max(len(rows) for w in pl["out"] for rows in w) if any(pl["out"]) else 0
     for k in range(3):
         for j0 in range(0, J, 16):
@@ -560,9 +583,20 @@ def _phase_body(a_, t, g, Lp, pl, nw):
             _lift_job(a_, t, Lp, rows, "    ")
         a_("  }")
     a_("  if (Tout == nullptr) return;")
-    a_("  // E: the updated field (re-read from L2) in the derivative frame into LDS")
-    a_("  __syncthreads();")
-    _stage_field(a_, t, nw, "V", "MV")
+    a_("  // E: the updated rows (still in registers) in the derivative frame into LDS")
+    a_("  {")
+    a_("    const R n00 = MV[0 * Ks + el], n01 = MV[1 * Ks + el], n02 = MV[2 * Ks + el];")
+    a_("    const R n11 = MV[3 * Ks + el], n12 = MV[4 * Ks + el], n22 = MV[5 * Ks + el];")
+    a_("    __syncthreads();")
+    for w in range(nw):
+        a_(f"    if (wave == {w}) {{")
+        for rows in pl["out"][w]:
+            for j, b in enumerate(rows):
+                a_(f"      wl[{b} * {LANES} + lane] = n00 * acc0_{j} + n01 * acc1_{j} + n02 * acc2_{j};")
+                a_(f"      wl[{N + b} * {LANES} + lane] = n01 * acc0_{j} + n11 * acc1_{j} + n12 * acc2_{j};")
+                a_(f"      wl[{2 * N + b} * {LANES} + lane] = n02 * acc0_{j} + n12 * acc1_{j} + n22 * acc2_{j};")
+        a_("    }")
+    a_("  }")
     a_("  __syncthreads();")
     a_("  // F: its traces for the next phase")
     _trace_stage(a_, t, g, pl, nw)
