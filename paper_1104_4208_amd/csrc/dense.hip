@@ -1,20 +1,19 @@
 // Dense reference-operator variant of one leapfrog phase on the matrix cores.
 //
-// The same operator as the sparse phase kernels, written as three dense
-// matrices that act on a tile of 64 elements at once (one element per GEMM
-// column), with 16-bit operands (BF16 or FP16) and FP32 accumulation on
+// The same operator as the sparse phase kernels, written as two dense matrices
+// that act on a tile of 64 elements at once (one element per GEMM column), with
+// 16-bit operands (BF16 or FP16) and FP32 accumulation on
 // v_mfma_f32_32x32x16_{bf16,f16}:
-//   AT   [8 NF x 3N]        own tangential traces   tau_{f,k} = T_f (g_{f,k} . w)
-//   ATg  [2 NF x 3N] x 4    neighbour traces on the neighbour's face g
+//   AT   [8 NF x 3N]        tangential traces on the four faces  tau_{f,k} = T_f (g_{f,k} . w)
 //   AU   [3N x (3N + 8NF)]  curl in the derivative frame plus the lifted jumps
 // where w = M S is the element's field in the derivative frame.  Section 3.2
 // evaluates these operators with O(N) recurrences; this variant applies them
 // as the O(N^2) matrix-vector products the paper avoids, batched over elements
 // so that they run on the matrix cores.  The field update itself stays FP32.
 //
-// Two kernels per phase: dense_trace writes the trace jumps (neighbour minus
-// own, FP32) to a scratch buffer J (8 NF x K); dense_update reads w and J and
-// adds sdt * (A_U [w; J]) to the updated field.
+// Two kernels per phase: dense_trace writes every element's own traces (FP32)
+// to a scratch buffer J (8 NF x K); dense_update forms the jumps (neighbour
+// minus own, read from J) and adds sdt * (A_U [w; jumps]) to the updated field.
 
 #include <hip/hip_runtime.h>
 
@@ -61,12 +60,16 @@ __device__ __forceinline__ void gemm_rowtile(const T* __restrict__ A, int KP, co
   const T* arow = A + (size_t)(rt * 32 + r) * KP + half * 8;
   const T* b0 = Bs + (size_t)r * (KP + kPad) + half * 8;
   const T* b1 = Bs + (size_t)(32 + r) * (KP + kPad) + half * 8;
+  // the operator fragment of the next k-step is fetched (from L2) one step ahead
+  V8 a = *reinterpret_cast<const V8*>(arow);
+#pragma unroll 4
   for (int ks = 0; ks < KP; ks += 16) {
-    const V8 a = *reinterpret_cast<const V8*>(arow + ks);
+    const V8 an = *reinterpret_cast<const V8*>(arow + (ks + 16 < KP ? ks + 16 : ks));
     const V8 x0 = *reinterpret_cast<const V8*>(b0 + ks);
     const V8 x1 = *reinterpret_cast<const V8*>(b1 + ks);
     acc0 = mfma(a, x0, acc0);
     acc1 = mfma(a, x1, acc1);
+    a = an;
   }
   for (int i = 0; i < 16; ++i) {
     const int row = rt * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
@@ -100,20 +103,19 @@ __device__ void fill_w(T* Bs, int KP, const float* __restrict__ U, const float* 
   }
 }
 
+// Own traces of a tile: J[row][e] = (AT w_e)[row], rows (f*2 + k)*NF + m, as one GEMM
+// of the trace table against the tile's field in the derivative frame.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) dense_trace_kernel(const float* __restrict__ U, const float* __restrict__ MU,
-                                                               const int* __restrict__ nbr, float wall, int K, int N,
-                                                               int NF, int KP, const T* __restrict__ AT,
-                                                               const T* __restrict__ ATg, float* __restrict__ J) {
+                                                               int K, int N, int NF, int KP,
+                                                               const T* __restrict__ AT, float* __restrict__ J) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* Bs = reinterpret_cast<T*>(smem);
   __shared__ int src[kTile];
   __shared__ float scl[kTile];
-  __shared__ int gface[kTile];
   const int wave = threadIdx.x >> 6;
   const int e0 = blockIdx.x * kTile;
   const size_t Ks = (size_t)K;
-  // own field; zero the padding columns once
   if (threadIdx.x < kTile) {
     const int e = e0 + threadIdx.x;
     src[threadIdx.x] = e < K ? e : -1;
@@ -130,51 +132,17 @@ __global__ void __launch_bounds__(kThreads) dense_trace_kernel(const float* __re
   for (int rt = wave; rt * 32 < M1; rt += 4)
     gemm_rowtile<T>(AT, KP, Bs, rt, [&](int row, int col, float v) {
       const int e = e0 + col;
-      if (row < M1 && e < K) J[(size_t)row * Ks + e] = -v;
+      if (row < M1 && e < K) J[(size_t)row * Ks + e] = v;
     });
-  const int M2 = 2 * NF;
-  for (int f = 0; f < 4; ++f) {
-    __syncthreads();
-    if (threadIdx.x < kTile) {
-      const int e = e0 + threadIdx.x;
-      int s = -1, g = f;
-      float c = 1.f;
-      if (e < K) {
-        const int code = nbr[(size_t)f * Ks + e];
-        if (code < 0) {
-          s = e;  // wall: ghost trace = wall * own trace on the same face
-          c = wall;
-        } else {
-          s = code >> 2;
-          g = code & 3;
-        }
-      }
-      src[threadIdx.x] = s;
-      scl[threadIdx.x] = c;
-      gface[threadIdx.x] = g;
-    }
-    __syncthreads();
-    fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
-    __syncthreads();  // also orders this tile's own-trace stores to J before the updates below
-    int present = 0;
-    for (int j = 0; j < kTile; ++j) present |= 1 << gface[j];
-    for (int g = 0; g < 4; ++g) {
-      if (!(present & (1 << g))) continue;
-      const T* A = ATg + (size_t)g * rup(M2, 32) * KP;
-      for (int rt = wave; rt * 32 < M2; rt += 4)
-        gemm_rowtile<T>(A, KP, Bs, rt, [&](int row, int col, float v) {
-          const int e = e0 + col;
-          if (row < M2 && e < K && gface[col] == g) J[(size_t)(f * M2 + row) * Ks + e] += v;
-        });
-    }
-  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __restrict__ U, float* __restrict__ V,
                                                                 const float* __restrict__ MU,
-                                                                const float* __restrict__ J, float sdt, int K, int N,
-                                                                int NF, int KP, const T* __restrict__ AU) {
+                                                                const int* __restrict__ nbr,
+                                                                const float* __restrict__ J, float sdt, float wall,
+                                                                int K, int N, int NF, int KP,
+                                                                const T* __restrict__ AU) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* Bs = reinterpret_cast<T*>(smem);
   __shared__ int src[kTile];
@@ -194,10 +162,18 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __r
   }
   __syncthreads();
   fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
+  // jumps of the tangential traces: neighbour minus own, (wall - 1) times own on walls
   for (int idx = threadIdx.x; idx < 8 * NF * kTile; idx += kThreads) {
     const int q = idx / kTile, j = idx % kTile;
     const int e = e0 + j;
-    Bs[(size_t)j * (KP + kPad) + 3 * N + q] = (T)(e < K ? J[(size_t)q * Ks + e] : 0.f);
+    float jump = 0.f;
+    if (e < K) {
+      const int f = q / (2 * NF), km = q - f * 2 * NF;
+      const float own = J[(size_t)q * Ks + e];
+      const int code = nbr[(size_t)f * Ks + e];
+      jump = code < 0 ? (wall - 1.f) * own : J[(size_t)((code & 3) * 2 * NF + km) * Ks + (code >> 2)] - own;
+    }
+    Bs[(size_t)j * (KP + kPad) + 3 * N + q] = (T)jump;
   }
   __syncthreads();
   const int M3 = 3 * N;
@@ -228,7 +204,6 @@ uint16_t to_f16(double x) {
 struct DenseOps {
   int p = 0, prec = 0, N = 0, NF = 0, KP1 = 0, KP2 = 0;
   void* AT = nullptr;
-  void* ATg = nullptr;
   void* AU = nullptr;
 };
 
@@ -241,15 +216,14 @@ int dense_build(int p, int prec, DenseOps** out, const char** err) {
   const OrderTables& t = kTables[p];
   const int N = t.N, NF = t.NF;
   const int KP1 = rup(3 * N, 16), KP2 = rup(3 * N + 8 * NF, 16);
-  const int M1P = rup(8 * NF, 32), M2P = rup(2 * NF, 32), M3P = rup(3 * N, 32);
-  std::vector<double> AT((size_t)M1P * KP1, 0.0), ATg((size_t)4 * M2P * KP1, 0.0), AU((size_t)M3P * KP2, 0.0);
+  const int M1P = rup(8 * NF, 32), M3P = rup(3 * N, 32);
+  std::vector<double> AT((size_t)M1P * KP1, 0.0), AU((size_t)M3P * KP2, 0.0);
   for (int f = 0; f < 4; ++f)
     for (int q = 0; q < t.nT[f]; ++q) {
       const SparseEntry& s = t.T[f][q];
       for (int k = 0; k < 2; ++k)
         for (int c = 0; c < 3; ++c) {
           AT[(size_t)((f * 2 + k) * NF + s.r) * KP1 + c * N + s.c] += t.g[f][k][c] * s.v;
-          ATg[((size_t)f * M2P + k * NF + s.r) * KP1 + c * N + s.c] += t.g[f][k][c] * s.v;
         }
       for (int k = 0; k < 3; ++k)
         for (int sc = 0; sc < 2; ++sc)
@@ -282,7 +256,6 @@ int dense_build(int p, int prec, DenseOps** out, const char** err) {
   d->KP1 = KP1;
   d->KP2 = KP2;
   int rc = conv(AT, &d->AT);
-  if (!rc) rc = conv(ATg, &d->ATg);
   if (!rc) rc = conv(AU, &d->AU);
   if (rc) {
     dense_free(d);
@@ -296,7 +269,6 @@ int dense_build(int p, int prec, DenseOps** out, const char** err) {
 void dense_free(DenseOps* d) {
   if (!d) return;
   (void)hipFree(d->AT);
-  (void)hipFree(d->ATg);
   (void)hipFree(d->AU);
   delete d;
 }
@@ -314,12 +286,12 @@ static hipError_t dense_phase_t(const DenseOps* d, const float* U, float* V, con
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)dense_update_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dense_trace_kernel<T>, dim3(blocks), dim3(kThreads), lds1, s, U, MU, nbr, wall, K, d->N, d->NF,
-                     d->KP1, (const T*)d->AT, (const T*)d->ATg, J);
+  hipLaunchKernelGGL(dense_trace_kernel<T>, dim3(blocks), dim3(kThreads), lds1, s, U, MU, K, d->N, d->NF, d->KP1,
+                     (const T*)d->AT, J);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dense_update_kernel<T>, dim3(blocks), dim3(kThreads), lds2, s, U, V, MU, (const float*)J, sdt, K,
-                     d->N, d->NF, d->KP2, (const T*)d->AU);
+  hipLaunchKernelGGL(dense_update_kernel<T>, dim3(blocks), dim3(kThreads), lds2, s, U, V, MU, nbr, (const float*)J, sdt,
+                     wall, K, d->N, d->NF, d->KP2, (const T*)d->AU);
   return hipGetLastError();
 }
 
