@@ -83,23 +83,21 @@ template <typename T>
 __device__ void fill_w(T* Bs, int KP, const float* __restrict__ U, const float* __restrict__ MU, int N, int K,
                        const int* src, const float* scale, int col0) {
   const size_t Ks = (size_t)K;
-  for (int idx = threadIdx.x; idx < N * kTile; idx += kThreads) {
-    const int a = idx / kTile, j = idx % kTile;
-    const int e = src[j];
-    float w0 = 0.f, w1 = 0.f, w2 = 0.f;
-    if (e >= 0) {
-      const float s0 = U[(size_t)a * Ks + e], s1 = U[(size_t)(N + a) * Ks + e], s2 = U[(size_t)(2 * N + a) * Ks + e];
-      const float m00 = MU[0 * Ks + e], m01 = MU[1 * Ks + e], m02 = MU[2 * Ks + e];
-      const float m11 = MU[3 * Ks + e], m12 = MU[4 * Ks + e], m22 = MU[5 * Ks + e];
-      const float c = scale[j];
-      w0 = c * (m00 * s0 + m01 * s1 + m02 * s2);
-      w1 = c * (m01 * s0 + m11 * s1 + m12 * s2);
-      w2 = c * (m02 * s0 + m12 * s1 + m22 * s2);
-    }
-    T* row = Bs + (size_t)j * (KP + kPad) + col0;
-    row[a] = (T)w0;
-    row[N + a] = (T)w1;
-    row[2 * N + a] = (T)w2;
+  // thread: element j, modes a0, a0 + 4, ...; the metric is read once and eight
+  // modes' loads are in flight together
+  const int j = threadIdx.x % kTile, a0 = threadIdx.x / kTile;
+  const int e = src[j];
+  const int es = e >= 0 ? e : 0;
+  const float c = e >= 0 ? scale[j] : 0.f;
+  const float m00 = c * MU[0 * Ks + es], m01 = c * MU[1 * Ks + es], m02 = c * MU[2 * Ks + es];
+  const float m11 = c * MU[3 * Ks + es], m12 = c * MU[4 * Ks + es], m22 = c * MU[5 * Ks + es];
+  T* row = Bs + (size_t)j * (KP + kPad) + col0;
+#pragma unroll 8
+  for (int a = a0; a < N; a += kThreads / kTile) {
+    const float s0 = U[(size_t)a * Ks + es], s1 = U[(size_t)(N + a) * Ks + es], s2 = U[(size_t)(2 * N + a) * Ks + es];
+    row[a] = (T)(m00 * s0 + m01 * s1 + m02 * s2);
+    row[N + a] = (T)(m01 * s0 + m11 * s1 + m12 * s2);
+    row[2 * N + a] = (T)(m02 * s0 + m12 * s1 + m22 * s2);
   }
 }
 
@@ -162,18 +160,26 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __r
   }
   __syncthreads();
   fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
-  // jumps of the tangential traces: neighbour minus own, (wall - 1) times own on walls
-  for (int idx = threadIdx.x; idx < 8 * NF * kTile; idx += kThreads) {
-    const int q = idx / kTile, j = idx % kTile;
+  // jumps of the tangential traces: neighbour minus own, (wall - 1) times own on walls;
+  // thread: element j, trace rows q0, q0 + 4, ... (eight rows' loads in flight together)
+  {
+    const int j = threadIdx.x % kTile, q0 = threadIdx.x / kTile;
     const int e = e0 + j;
-    float jump = 0.f;
-    if (e < K) {
-      const int f = q / (2 * NF), km = q - f * 2 * NF;
-      const float own = J[(size_t)q * Ks + e];
-      const int code = nbr[(size_t)f * Ks + e];
-      jump = code < 0 ? (wall - 1.f) * own : J[(size_t)((code & 3) * 2 * NF + km) * Ks + (code >> 2)] - own;
+    const int es = e < K ? e : K - 1;
+    T* row = Bs + (size_t)j * (KP + kPad) + 3 * N;
+    for (int f = 0; f < 4; ++f) {
+      const int code = nbr[(size_t)f * Ks + es];
+      const size_t nsrc = code < 0 ? es : (size_t)(code >> 2);
+      const int nrow0 = code < 0 ? f * 2 * NF : (code & 3) * 2 * NF;
+      const float cw = code < 0 ? wall - 1.f : -1.f;
+      const float cn = code < 0 ? 0.f : 1.f;
+#pragma unroll 8
+      for (int km = q0; km < 2 * NF; km += kThreads / kTile) {
+        const float own = J[(size_t)(f * 2 * NF + km) * Ks + es];
+        const float nb = J[(size_t)(nrow0 + km) * Ks + nsrc];
+        row[f * 2 * NF + km] = (T)(e < K ? cn * nb + cw * own : 0.f);
+      }
     }
-    Bs[(size_t)j * (KP + kPad) + 3 * N + q] = (T)jump;
   }
   __syncthreads();
   const int M3 = 3 * N;
