@@ -32,7 +32,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kTile = 64;      // elements per workgroup (two 32-wide MFMA column tiles)
-constexpr int kThreads = 256;  // four waves
+constexpr int kThreads = 1024; // sixteen waves (one WG per CU: the waves hide each other's L2 latency)
 constexpr int kPad = 8;        // extra 16-bit entries per LDS row
 
 template <typename T> struct Vec8;
@@ -49,14 +49,17 @@ __device__ __forceinline__ f32x16 mfma(f16x8 a, f16x8 b, f32x16 c) {
 __host__ __device__ constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
 
 // Tile of 64 elements: rows rt*32.. of A (row-major, lda = KP) times the LDS
-// operand Bs (element-major rows of stride KP + kPad).  Calls out(row, col, v)
-// for the 32 x 64 result block owned by this lane.
-template <typename T, typename Out>
-__device__ __forceinline__ void gemm_rowtile(const T* __restrict__ A, int KP, const T* Bs, int rt, Out out) {
+// operand Bs (element-major rows of stride KP + kPad).  acc0 / acc1 receive the
+// 32 x 32 blocks of element columns 0..31 / 32..63; entry i of this lane is row
+// rt*32 + 8*(i/4) + 4*(lane/32) + i%4, column lane%32.
+template <typename T>
+__device__ __forceinline__ void gemm_acc(const T* __restrict__ A, int KP, const T* Bs, int rt, f32x16& acc0,
+                                         f32x16& acc1) {
   typedef typename Vec8<T>::type V8;
   const int l = threadIdx.x & 63;
   const int half = l >> 5, r = l & 31;
-  f32x16 acc0 = {}, acc1 = {};
+  acc0 = f32x16{};
+  acc1 = f32x16{};
   const T* arow = A + (size_t)(rt * 32 + r) * KP + half * 8;
   const T* b0 = Bs + (size_t)r * (KP + kPad) + half * 8;
   const T* b1 = Bs + (size_t)(32 + r) * (KP + kPad) + half * 8;
@@ -71,12 +74,9 @@ __device__ __forceinline__ void gemm_rowtile(const T* __restrict__ A, int KP, co
     acc1 = mfma(a, x1, acc1);
     a = an;
   }
-  for (int i = 0; i < 16; ++i) {
-    const int row = rt * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
-    out(row, r, acc0[i]);
-    out(row, 32 + r, acc1[i]);
-  }
 }
+
+__device__ __forceinline__ int acc_row(int rt, int i) { return rt * 32 + 8 * (i >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (i & 3); }
 
 // Fill one LDS row block with w = scale * M S of the given elements (16-bit).
 template <typename T>
@@ -127,11 +127,17 @@ __global__ void __launch_bounds__(kThreads) dense_trace_kernel(const float* __re
   fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
   __syncthreads();
   const int M1 = 8 * NF;
-  for (int rt = wave; rt * 32 < M1; rt += 4)
-    gemm_rowtile<T>(AT, KP, Bs, rt, [&](int row, int col, float v) {
-      const int e = e0 + col;
-      if (row < M1 && e < K) J[(size_t)row * Ks + e] = v;
-    });
+  const int r = threadIdx.x & 31;
+  for (int rt = wave; rt * 32 < M1; rt += kThreads / 64) {
+    f32x16 acc0, acc1;
+    gemm_acc<T>(AT, KP, Bs, rt, acc0, acc1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = acc_row(rt, i);
+      if (row < M1 && e0 + r < K) J[(size_t)row * Ks + e0 + r] = acc0[i];
+      if (row < M1 && e0 + 32 + r < K) J[(size_t)row * Ks + e0 + 32 + r] = acc1[i];
+    }
+  }
 }
 
 template <typename T>
@@ -183,11 +189,25 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __r
   }
   __syncthreads();
   const int M3 = 3 * N;
-  for (int rt = wave; rt * 32 < M3; rt += 4)
-    gemm_rowtile<T>(AU, KP, Bs, rt, [&](int row, int col, float v) {
-      const int e = e0 + col;
-      if (row < M3 && e < K) V[(size_t)row * Ks + e] += sdt * v;
-    });
+  const int r = threadIdx.x & 31;
+  for (int rt = wave; rt * 32 < M3; rt += kThreads / 64) {
+    f32x16 acc0, acc1;
+    gemm_acc<T>(AU, KP, Bs, rt, acc0, acc1);
+    // all old values of the block first, then the updates (no load waits behind a store)
+    float old0[16], old1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = acc_row(rt, i);
+      old0[i] = (row < M3 && e0 + r < K) ? V[(size_t)row * Ks + e0 + r] : 0.f;
+      old1[i] = (row < M3 && e0 + 32 + r < K) ? V[(size_t)row * Ks + e0 + 32 + r] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = acc_row(rt, i);
+      if (row < M3 && e0 + r < K) V[(size_t)row * Ks + e0 + r] = old0[i] + sdt * acc0[i];
+      if (row < M3 && e0 + 32 + r < K) V[(size_t)row * Ks + e0 + 32 + r] = old1[i] + sdt * acc1[i];
+    }
+  }
 }
 
 uint16_t to_bf16(double x) {
