@@ -11,7 +11,8 @@ struct DenseOps;
 // DGM_ERR_* code with *err set.
 int dense_build(int p, int prec, DenseOps** out, const char** err);
 void dense_free(DenseOps* d);
-// FP32 scratch the phase needs for the own traces of all elements (8 NF x K floats).
+// FP32 scratch the phase needs for the traces of all elements (whole 64-element tiles
+// in the trace layout of launch.h).
 size_t dense_scratch_floats(const DenseOps* d, int64_t K);
 // One phase on stored-frame FP32 fields: V += sdt * rate(U); J is scratch.
 hipError_t dense_phase(const DenseOps* d, const float* U, float* V, const float* MU, const int* nbr, float sdt,

@@ -11,9 +11,10 @@
 // as the O(N^2) matrix-vector products the paper avoids, batched over elements
 // so that they run on the matrix cores.  The field update itself stays FP32.
 //
-// Two kernels per phase: dense_trace writes every element's own traces (FP32)
-// to a scratch buffer J (8 NF x K); dense_update forms the jumps (neighbour
-// minus own, read from J) and adds sdt * (A_U [w; jumps]) to the updated field.
+// Two kernels per phase: dense_trace writes every element's own traces (FP32) to a
+// scratch buffer J in the trace layout of the sparse path; dense_update forms the
+// jumps (neighbour minus own, read from J) and adds sdt * (A_U [w; jumps]) to the
+// updated field.
 
 #include <hip/hip_runtime.h>
 
@@ -23,6 +24,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "launch.h"
 #include "generated/tables.inc"
 
 namespace {
@@ -63,16 +65,21 @@ __device__ __forceinline__ void gemm_acc(const T* __restrict__ A, int KP, const 
   const T* arow = A + (size_t)(rt * 32 + r) * KP + half * 8;
   const T* b0 = Bs + (size_t)r * (KP + kPad) + half * 8;
   const T* b1 = Bs + (size_t)(32 + r) * (KP + kPad) + half * 8;
-  // the operator fragment of the next k-step is fetched (from L2) one step ahead
-  V8 a = *reinterpret_cast<const V8*>(arow);
+  // operator fragments are fetched (from L2) three k-steps ahead
+  const int last = KP - 16;
+  V8 a0 = *reinterpret_cast<const V8*>(arow);
+  V8 a1 = *reinterpret_cast<const V8*>(arow + (16 < last ? 16 : last));
+  V8 a2 = *reinterpret_cast<const V8*>(arow + (32 < last ? 32 : last));
 #pragma unroll 4
   for (int ks = 0; ks < KP; ks += 16) {
-    const V8 an = *reinterpret_cast<const V8*>(arow + (ks + 16 < KP ? ks + 16 : ks));
+    const V8 a3 = *reinterpret_cast<const V8*>(arow + (ks + 48 < last ? ks + 48 : last));
     const V8 x0 = *reinterpret_cast<const V8*>(b0 + ks);
     const V8 x1 = *reinterpret_cast<const V8*>(b1 + ks);
-    acc0 = mfma(a, x0, acc0);
-    acc1 = mfma(a, x1, acc1);
-    a = an;
+    acc0 = mfma(a0, x0, acc0);
+    acc1 = mfma(a0, x1, acc1);
+    a0 = a1;
+    a1 = a2;
+    a2 = a3;
   }
 }
 
@@ -127,15 +134,23 @@ __global__ void __launch_bounds__(kThreads) dense_trace_kernel(const float* __re
   fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
   __syncthreads();
   const int M1 = 8 * NF;
+  // traces go to the tile-blocked, quad-interleaved layout of the sparse path
+  // (launch.h): value c = k * NFP + m of face f, lane l at ((f FQ + c/4) 64 + l) 4 + c%4
   const int r = threadIdx.x & 31;
+  const int NFP = trace_face_stride(NF) / 2, FQ = NFP / 2;
+  float* Jt = J + (size_t)blockIdx.x * kTile * trace_elem_stride(NF);
   for (int rt = wave; rt * 32 < M1; rt += kThreads / 64) {
     f32x16 acc0, acc1;
     gemm_acc<T>(AT, KP, Bs, rt, acc0, acc1);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = acc_row(rt, i);
-      if (row < M1 && e0 + r < K) J[(size_t)row * Ks + e0 + r] = acc0[i];
-      if (row < M1 && e0 + 32 + r < K) J[(size_t)row * Ks + e0 + 32 + r] = acc1[i];
+      if (row < M1) {
+        const int f = row / (2 * NF), km = row - f * 2 * NF, k = km >= NF, c = km + k * (NFP - NF);
+        const int off = ((f * FQ + (c >> 2)) * kTile) * 4 + (c & 3);
+        Jt[off + r * 4] = acc0[i];
+        Jt[off + (32 + r) * 4] = acc1[i];
+      }
     }
   }
 }
@@ -166,25 +181,29 @@ __global__ void __launch_bounds__(kThreads) dense_update_kernel(const float* __r
   }
   __syncthreads();
   fill_w<T>(Bs, KP, U, MU, N, K, src, scl, 0);
-  // jumps of the tangential traces: neighbour minus own, (wall - 1) times own on walls;
-  // thread: element j, trace rows q0, q0 + 4, ... (eight rows' loads in flight together)
+  // jumps of the tangential traces, neighbour minus own ((wall - 1) times own on walls),
+  // from the traces of all elements in the tile-blocked layout: per lane one 16-byte
+  // load of the own and one of the neighbour's chunk (four face modes of one tangent)
   {
     const int j = threadIdx.x % kTile, q0 = threadIdx.x / kTile;
     const int e = e0 + j;
     const int es = e < K ? e : K - 1;
+    const int NFP = trace_face_stride(NF) / 2, FQ = NFP / 2, ES = trace_elem_stride(NF);
+    const float* own = J + (size_t)(es >> 6) * kTile * ES + (size_t)(es & 63) * 4;
     T* row = Bs + (size_t)j * (KP + kPad) + 3 * N;
-    for (int f = 0; f < 4; ++f) {
+#pragma unroll 4
+    for (int q = q0; q < 4 * FQ; q += kThreads / kTile) {
+      const int f = q / FQ, c = 4 * (q - f * FQ), k = c >= NFP, m = c - k * NFP;
       const int code = nbr[(size_t)f * Ks + es];
-      const size_t nsrc = code < 0 ? es : (size_t)(code >> 2);
-      const int nrow0 = code < 0 ? f * 2 * NF : (code & 3) * 2 * NF;
-      const float cw = code < 0 ? wall - 1.f : -1.f;
-      const float cn = code < 0 ? 0.f : 1.f;
-#pragma unroll 8
-      for (int km = q0; km < 2 * NF; km += kThreads / kTile) {
-        const float own = J[(size_t)(f * 2 * NF + km) * Ks + es];
-        const float nb = J[(size_t)(nrow0 + km) * Ks + nsrc];
-        row[f * 2 * NF + km] = (T)(e < K ? cn * nb + cw * own : 0.f);
-      }
+      const int nb = code < 0 ? es : code >> 2, gf = code < 0 ? f : code & 3;
+      const float4 o = *reinterpret_cast<const float4*>(own + (size_t)q * kTile * 4);
+      const float4 t = *reinterpret_cast<const float4*>(J + (size_t)(nb >> 6) * kTile * ES +
+                                                        ((size_t)(gf * FQ + (q - f * FQ)) * kTile + (nb & 63)) * 4);
+      const float cw = code < 0 ? wall - 1.f : -1.f, cn = code < 0 ? 0.f : 1.f;
+      const float v[4] = {cn * t.x + cw * o.x, cn * t.y + cw * o.y, cn * t.z + cw * o.z, cn * t.w + cw * o.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (m + i < NF) row[(f * 2 + k) * NF + m + i] = (T)(e < K ? v[i] : 0.f);
     }
   }
   __syncthreads();
@@ -299,7 +318,9 @@ void dense_free(DenseOps* d) {
   delete d;
 }
 
-size_t dense_scratch_floats(const DenseOps* d, int64_t K) { return (size_t)8 * d->NF * (size_t)K; }
+size_t dense_scratch_floats(const DenseOps* d, int64_t K) {
+  return (size_t)((K + kTile - 1) / kTile) * kTile * trace_elem_stride(d->NF);
+}
 
 template <typename T>
 static hipError_t dense_phase_t(const DenseOps* d, const float* U, float* V, const float* MU, const int* nbr,
