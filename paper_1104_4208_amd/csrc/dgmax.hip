@@ -832,6 +832,7 @@ struct dgm_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
+  unsigned live_orders = 0;  // orders with active slots in the captured graph
 };
 
 namespace {
@@ -847,7 +848,7 @@ int batch_capture(dgm_batch* b) {
   for (int sub = 0; sub < b->chunk && err == hipSuccess; ++sub)
     for (int phase = 0; phase < 2 && err == hipSuccess; ++phase)
       for (int p = 1; p <= DGM_MAX_ORDER_F32 && err == hipSuccess; ++p) {
-        if (b->cap_tiles[p] <= 0) continue;
+        if (b->cap_tiles[p] <= 0 || !(b->live_orders & (1u << p))) continue;
         BatchArgs a;
         a.slots = b->d_slots[p];
         a.tile0 = b->d_tile0[p];
@@ -963,12 +964,20 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
       b->cap_tiles[p] = std::max(nt, b->cap_tiles[p] + b->cap_tiles[p] / 2);
       b->dirty = true;
     }
-    if (b->cap_slots[p] > 0) {
+    if (ns > 0) {  // orders without active slots are not in the graph
       b->h_n[p] = ns;
-      if (ns) HIP_TRY(hipMemcpyAsync(b->d_slots[p], b->h_slots[p].data(), ns * sizeof(BatchSlot), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b->d_slots[p], b->h_slots[p].data(), ns * sizeof(BatchSlot), hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(b->d_tile0[p], b->h_tile0[p].data(), (ns + 1) * sizeof(int), hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(b->d_n[p], &b->h_n[p], sizeof(int), hipMemcpyHostToDevice, s));
     }
+  }
+  // the graph covers only the orders that have active slots: re-capture when that set changes
+  unsigned live = 0;
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p)
+    if (!b->h_slots[p].empty()) live |= 1u << p;
+  if (live != b->live_orders) {
+    b->live_orders = live;
+    b->dirty = true;
   }
   int rc;
   if (b->dirty && (rc = batch_capture(b))) return rc;
