@@ -109,9 +109,10 @@ int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void
  *     H <- H + dt M_mu^{-1} C E,   E <- E - dt M_eps^{-1} C^T H.
  * dt is the caller's (see dgm_estimate_dt); nsteps >= 0.  Each half step is one
  * kernel that also writes the tangential face traces of the field it updated
- * (element-major, 2 (p+1)(p+2) values per face rounded up to a multiple of 4)
- * for the neighbours in the next half step; the handle keeps these two buffers
- * (allocated on first use, 2 K x 4 x that stride values of dtype). */
+ * (per element and face two tangents over the (p+1)(p+2)/2 face modes, each
+ * padded to a multiple of 4) for the neighbours in the next half step; the
+ * handle keeps these two buffers (allocated on first use, K rounded up to a
+ * multiple of 64, times 8 x the padded face-mode count, values of dtype each). */
 int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
 
 /* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),

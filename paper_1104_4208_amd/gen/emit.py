@@ -1,25 +1,28 @@
-"""Emit the per-order HIP phase kernels as straight-line code.
+"""Emit the per-order HIP kernels (phase, batched phase, traces) as straight-line code.
 
 Section 3.2.2 describes the reference implementation as C++ template
 meta-programming that generates optimised code for every order up to an
 a-priori maximum.  This module plays that role for CDNA4: for each order p
-it writes one kernel body in which every sparse operator entry of
-gen/tables.py is an FMA with a literal coefficient, so the 64 lanes of a
-wavefront (one element per lane) run an identical, branch-free instruction
-stream with all data in registers.
+it writes kernel bodies in which every sparse operator entry of gen/tables.py
+is an FMA with a literal coefficient.  One element per lane, 64 elements per
+workgroup tile; the waves of a workgroup split the operator rows between them
+(plan), and the tile's field and trace jumps are shared through LDS.
 
-Kernel contract (one leapfrog half step, "phase"):
+Phase contract (one leapfrog half step):
   U  (3,N,K)  stored-frame coefficients of the field that is differentiated
   V  (3,N,K)  stored-frame coefficients of the field that is updated, in place
-  MU (6,K)    symmetric conversion w = MU S (derivative frame) for U
+  MU, MV (6,K)  symmetric conversions w = M S into the derivative frame
   nbr(4,K)    neighbour code nb*4 + local face of nb, or -1 on a wall
+  Tin         tangential traces of U (trace buffer, layout in trace_strides)
+  Tout        traces of the updated V for the next phase, or nullptr
   sdt         -dt for the H update, +dt for the E update
   wall        ghost factor on walls: the jump is (wall-1) * own trace
               (E_nb = -E gives wall = -1; H_nb = H gives wall = +1)
   V_k += sdt * ( c_k + sum_f T_f^T ( Lp_f[k,0] dtau_f0 + Lp_f[k,1] dtau_f1 ) )
-where dtau_fk = tau_fk(neighbour) - tau_fk(own) are the jumps of the two
-tangential traces (u . t1, u . t2) of face f, which both sides compute in the
-same (s,t) parametrisation because vertices are sorted by global id.
+where c is the curl in the derivative frame and dtau_fk = tau_fk(neighbour) -
+tau_fk(own) are the jumps of the two tangential traces (u . t1, u . t2) of
+face f, which both sides compute in the same (s,t) parametrisation because
+vertices are sorted by global id.
 """
 from __future__ import annotations
 
@@ -47,15 +50,11 @@ def _fma(acc, coef, x):
     return f"{acc} += {_lit(coef)} * {x};"
 
 
-LANES = 64
+LANES = 64               # elements per workgroup tile (one per lane)
 LDS_BUDGET = 160 * 1024  # bytes of LDS per compute unit
-F64_MAX_ORDER = 6   # highest order also instantiated in FP64 (the staged field, 3N x 64 doubles, must fit in LDS)
-
-
-TRACE_ROWS = 32   # face modes per trace job (bounds the job's accumulators)
-
-
-LDS_GROUP = 8     # mode blocks per basic block in a stream
+F64_MAX_ORDER = 6        # highest order also instantiated in FP64 (its staged field must fit in LDS)
+TRACE_ROWS = 32          # face modes per trace job (bounds the job's accumulators)
+LDS_GROUP = 8            # mode blocks per basic block in a stream
 
 
 class _Stream:
