@@ -18,7 +18,10 @@ field, read and write the updated field, 24 B of metric and 16 B of neighbour
 codes); its average duration is measured live with HIP events on the stream it
 is launched on (difference of a long and a one-step run, so the frame
 conversions at the ends cancel).  cpu_baseline: the FP64 oracle timed on a
-bounded sample of the same workload (smaller cube, same order and recipe).
+bounded sample of the same workload (smaller cube, same order and recipe); the
+same leg (the only code here that runs the oracle) reports the FP32 error against
+the oracle on that sample, and at p = 8 for the sparse and dense paths, under
+"accuracy".
 """
 from __future__ import annotations
 
@@ -83,11 +86,22 @@ def build_inputs():
     return w, d, E0
 
 
-def cpu_baseline(target_seconds: float):
-    """FP64 oracle on a bounded sample: the same recipe on a 4^3-cell cube (384 tets),
-    p = 6, as many steps as fit in about target_seconds."""
-    import oracle
+def oracle_leg(target_seconds: float, dense: bool):
+    """Everything that runs the FP64 oracle (nothing else in this file does).
+
+    cpu_baseline: the oracle timed on a bounded sample of the workload (the same
+    recipe on a 4^3-cell cube, 384 tets, p = 6), as many steps as fit in about
+    target_seconds.  accuracy: the FP32 library run on the same sample and steps
+    against the oracle (relative energy-norm error), and, with `dense`, one operator
+    application of the p = 8 workload on sampled elements (patch meshes) for the
+    sparse FP32 path and the dense BF16 / FP16 variants."""
+    import torch
+
+    import paper_1104_4208_amd as P
     import synth
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_helpers import Pair, patch, rel_err
 
     try:
         from threadpoolctl import threadpool_info
@@ -99,10 +113,12 @@ def cpu_baseline(target_seconds: float):
     verts, tets = synth.kuhn_mesh(4, 0.1, rng)
     K = tets.shape[0]
     eps = rng.choice([1.0, 4.0], size=K)
-    s = oracle.Solver(oracle.build_mesh(verts, np.sort(tets, axis=1)), 6, eps)
+    pr = Pair(verts, tets, 6, eps)
+    s = pr.s
     fld = synth.three_mode_sum(rng)
     E = s.project(fld.E)
     H = np.zeros_like(E)
+    E0, H0 = E.copy(), H.copy()
     dt = 1e-3
     E, H = s.step(E, H, dt, 1)  # warm caches
     n, t0 = 0, time.perf_counter()
@@ -111,22 +127,48 @@ def cpu_baseline(target_seconds: float):
         n += 1
     el = time.perf_counter() - t0
     rate = 6 * s.N * K * n / el
-    return {"value": rate, "unit": "DOF-updates/s", "cores": int(cores), "kind": "oracle",
+    base = {"value": rate, "unit": "DOF-updates/s", "cores": int(cores), "kind": "oracle",
             "sample": f"FP64 oracle, 4^3 x 6 = {K} jittered tets, p=6, eps in {{1,4}}, {n} steps in {el:.1f} s"}
+    # the FP32 library on the same sample, initial data and steps
+    m = P.Mesh(verts, tets).set_order(6).set_material(eps, None)
+    Eg = torch.tensor(np.ascontiguousarray(pr.to_cov(E0)), dtype=torch.float32, device="cuda")
+    Hg = torch.tensor(np.ascontiguousarray(pr.to_cov(H0)), dtype=torch.float32, device="cuda")
+    m.step(Eg, Hg, dt, n + 1)
+    torch.cuda.synchronize()
+    err = s.rel_error(pr.to_phys(Eg.double().cpu().numpy()), pr.to_phys(Hg.double().cpu().numpy()), E, H)
+    acc = {"fp32_vs_oracle_p6_rel_energy_err": err, "steps": n + 1,
+           "sample": f"the cpu_baseline sample ({K} tets, p=6), same initial field, dt = {dt}"}
+    if dense:
+        w = synth.WORKLOADS["cube24_p8_dense"]
+        d = synth.build_workload(w)
+        verts8, tets8 = d["verts"], d["tets"]
+        K8, N8 = tets8.shape[0], P.num_modes(8)
+        m8 = P.Mesh(verts8, tets8).set_order(8)
+        r8 = np.random.default_rng(8)
+        Hr = torch.tensor(np.ascontiguousarray(r8.standard_normal((3, N8, K8))), dtype=torch.float32, device="cuda")
+        centers = np.arange(0, K8, K8 // 8)
+        keep, ptets, pos = patch(tets8, centers)
+        p8 = Pair(verts8, ptets, 8)
+        ref = p8.to_cov(p8.s.rhs_e(p8.to_phys(Hr[:, :, keep].double().cpu().numpy())))[:, :, pos]
+        for name, prec in (("fp32_sparse", None), ("bf16_dense", P.DGM_BF16), ("fp16_dense", P.DGM_F16)):
+            dE, _ = m8.apply_curl(None, Hr) if prec is None else m8.apply_curl_dense(None, Hr, prec=prec)
+            torch.cuda.synchronize()
+            acc[f"p8_apply_rel_err_vs_oracle_{name}"] = rel_err(dE[:, :, centers].double().cpu().numpy(), ref)
+        acc["p8_sample"] = f"dE = rate(random H) on {len(centers)} elements of the 24^3 x 6 mesh, oracle on patch meshes"
+    return base, acc
 
 
 def dense_comparison(steps: int):
     """p = 8 workload (24^3 x 6 = 82,944 tets, random modal data, seed 4): the FP32
     sparse path against the dense matrix-core variant with BF16 and FP16 operands.
-    Reports time per step, DOF-updates/s, the error of one operator application
-    against the FP64 oracle on sampled elements, and the energy-norm distance of
-    each dense run from the FP32 run after `steps` steps."""
+    Reports time per step, DOF-updates/s, the difference of one dense operator
+    application from the FP32 one, and the energy-norm distance of each dense run
+    from the FP32 run after `steps` steps (errors against the oracle are in the
+    accuracy block of the oracle leg)."""
     import torch
 
-    import oracle
     import paper_1104_4208_amd as P
     import synth
-    from paper_1104_4208_amd.gen.basis import volume_modes
 
     w = synth.WORKLOADS["cube24_p8_dense"]
     d = synth.build_workload(w)
@@ -147,24 +189,11 @@ def dense_comparison(steps: int):
     E /= math.sqrt(W0)  # rescaled to W = 1
     dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
     out = {"workload": "pec_cube_kuhn24_p8_random_modes", "tets": K, "p": p, "dofs": 6 * N * K, "steps": steps, "dt": dt}
-    # sampled operator error against the oracle
-    centers = np.arange(0, K, K // 8)
-    import sys as _s
-    _s.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_helpers import Pair, patch, rel_err
-
-    keep, ptets, pos = patch(tets, centers)
-    pr = Pair(verts, ptets, p)
     Hrand = torch.tensor(np.ascontiguousarray(rng.standard_normal((3, N, K))), dtype=torch.float32, device="cuda")
-    ref_de = pr.to_cov(pr.s.rhs_e(pr.to_phys(Hrand[:, :, keep].double().cpu().numpy())))[:, :, pos]
+    ref, _ = m.apply_curl(None, Hrand)
+    scale = float(ref.abs().max())
     runs = {}
     for name, prec in (("fp32_sparse", None), ("bf16_dense", P.DGM_BF16), ("fp16_dense", P.DGM_F16)):
-        if prec is None:
-            dE, _ = m.apply_curl(None, Hrand)
-        else:
-            dE, _ = m.apply_curl_dense(None, Hrand, prec=prec)
-        torch.cuda.synchronize()
-        err1 = rel_err(dE[:, :, centers].double().cpu().numpy(), ref_de)
         Ei, Hi = E.clone(), H.clone()
         stepf = (lambda a, b, n: m.step(a, b, dt, n)) if prec is None else (lambda a, b, n, q=prec: m.step_dense(a, b, dt, n, prec=q))
         stepf(Ei, Hi, 2)
@@ -177,8 +206,10 @@ def dense_comparison(steps: int):
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3
         runs[name] = (Ei, Hi)
-        out[name] = {"ms_per_step": sec / steps * 1e3, "dof_updates_per_s": 6 * N * K * steps / sec,
-                     "apply_rel_err_vs_oracle": err1}
+        out[name] = {"ms_per_step": sec / steps * 1e3, "dof_updates_per_s": 6 * N * K * steps / sec}
+        if prec is not None:
+            dE, _ = m.apply_curl_dense(None, Hrand, prec=prec)
+            out[name]["apply_rel_diff_from_fp32"] = float((dE - ref).abs().max()) / scale
     Es, Hs = runs["fp32_sparse"]
     Ws, _ = m.energy(Es, Hs)
     for name in ("bf16_dense", "fp16_dense"):
@@ -272,7 +303,7 @@ def main():
                        "short; `python -m paper_1104_4208_amd.serve` runs the full 256-request trace")
         out["serving"] = rep
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+        out["cpu_baseline"], out["accuracy"] = oracle_leg(a.cpu_seconds, dense=not a.no_dense)
     print(json.dumps(out), flush=True)
 
 

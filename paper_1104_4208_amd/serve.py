@@ -1,5 +1,8 @@
 """Continuous-batching serving loop for many cavity solves on one GPU.
 
+Interface: Scheduler(hbm_budget_bytes, steps_per_launch).submit(mesh, p, eps, mu,
+E0, H0, dt, nsteps) -> Ticket; Ticket.result() -> (E, H, (W, Q), latency).
+
 Requests (a jittered cube mesh, order p, permittivity eps, step count) arrive
 over time.  The server admits them into batch slots whenever the HBM budget
 allows, advances every active slot together with one HIP-graph launch per
@@ -32,6 +35,14 @@ from . import dgmax as D
 from .project import project_covariant
 
 
+def device_bytes(K: int, p: int) -> int:
+    """Device memory of one FP32 solve: the state (E, H), the two trace buffers and
+    the per-element geometry the library keeps for the mesh handle."""
+    nf = D.num_face_modes(p)
+    trace = ((K + 63) // 64) * 64 * 4 * 2 * ((nf + 3) // 4 * 4)
+    return 2 * 3 * D.num_modes(p) * K * 4 + 2 * trace * 4 + K * 260
+
+
 @dataclass
 class Request:
     rid: int
@@ -59,11 +70,7 @@ class Request:
         return self.dofs * self.steps
 
     def device_bytes(self):
-        """State (E, H FP32), the two trace buffers and the per-element geometry the
-        library keeps for the mesh handle."""
-        nf = D.num_face_modes(self.p)
-        trace = ((self.K + 63) // 64) * 64 * 4 * 2 * ((nf + 3) // 4 * 4)
-        return 2 * 3 * D.num_modes(self.p) * self.K * 4 + 2 * trace * 4 + self.K * 260
+        return device_bytes(self.K, self.p)
 
 
 def make_trace(num=256, rate=50.0, seed=5, n_range=(4, 24), p_range=(2, 8), eps_choices=(1.0, 2.0, 4.0),
@@ -177,6 +184,83 @@ class Server:
         return {"mode": mode, "requests": len(reqs), "makespan_s": makespan, "dof_updates": work,
                 "dof_updates_per_s": work / makespan, "p50_latency_s": _percentile(lat, 50),
                 "p99_latency_s": _percentile(lat, 99), "mean_latency_s": float(np.mean(lat))}, states
+
+
+class Ticket:
+    """Handle of one submitted solve.  result() drives the server until this solve
+    has finished and returns (E, H, (W, Q), latency_s): the final covariant fields
+    (device tensors, FP32), the FP64 energy W and leapfrog invariant Q at the end,
+    and the time from submission to completion."""
+
+    def __init__(self, server, tid):
+        self.server, self.tid = server, tid
+
+    def done(self) -> bool:
+        return self.tid in self.server._results
+
+    def result(self):
+        while not self.done():
+            self.server.poll()
+        return self.server._results[self.tid]
+
+
+class Scheduler:
+    """Submission interface of the batched server: solves are queued by submit(),
+    admitted into batch slots while the HBM budget allows (the oldest first; one
+    solve is always admitted when none is running), and advanced together by
+    poll(), chunk steps per call."""
+
+    def __init__(self, hbm_budget_bytes: int, steps_per_launch: int = 20):
+        self.budget = int(hbm_budget_bytes)
+        self.batch = D.Batch(int(steps_per_launch))
+        self._queue = []
+        self._live = {}
+        self._results = {}
+        self._used = 0
+        self._next = 0
+
+    def submit(self, verts, tets, p, eps, mu, E0, H0, dt, nsteps) -> Ticket:
+        """verts/tets: host mesh arrays; eps, mu: per-element arrays or scalars (None
+        means 1); E0, H0: covariant (3, N, K) FP32 initial fields (host arrays or
+        device tensors, copied); dt and nsteps of the leapfrog run."""
+        tid = self._next
+        self._next += 1
+        self._queue.append((tid, time.perf_counter(), verts, tets, p, eps, mu, E0, H0, dt, nsteps))
+        return Ticket(self, tid)
+
+    def poll(self):
+        """Admit what fits, advance every active solve by one chunk, collect results."""
+        import torch
+
+        while self._queue:
+            tid, t0, verts, tets, p, eps, mu, E0, H0, dt, nsteps = self._queue[0]
+            K = np.asarray(tets).shape[0]
+            need = device_bytes(K, p)
+            if self._live and self._used + need > self.budget:
+                break
+            self._queue.pop(0)
+            full = lambda v: None if v is None else np.broadcast_to(np.asarray(v, dtype=np.float64), (K,)).copy()
+            m = D.Mesh(verts, tets).set_order(p).set_material(full(eps), full(mu))
+            E = torch.as_tensor(E0, dtype=torch.float32, device="cuda").clone().contiguous()
+            H = torch.as_tensor(H0, dtype=torch.float32, device="cuda").clone().contiguous()
+            sid = self.batch.add(m, E, H, dt, nsteps)
+            self._live[sid] = (tid, t0, m, E, H, dt, need)
+            self._used += need
+        if self._live:
+            self.batch.advance()
+        for sid in self.batch.take_finished():
+            tid, t0, m, E, H, dt, need = self._live.pop(sid)
+            energies = m.energy(E, H, dt=dt)
+            self._results[tid] = (E, H, energies, time.perf_counter() - t0)
+            self._used -= need
+            m.close()
+
+    def drain(self):
+        while self._queue or self._live:
+            self.poll()
+
+    def close(self):
+        self.batch.close()
 
 
 def closed_form_error(req, E, H):

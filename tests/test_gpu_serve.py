@@ -66,3 +66,26 @@ def test_small_trace_both_modes():
         assert torch.equal(sb[rid][0], ss[rid][0]) and torch.equal(sb[rid][1], ss[rid][1])
     print(rb, rs)
     assert rb["p99_latency_s"] >= rb["p50_latency_s"] > 0
+
+
+def test_submit_tickets_match_alone():
+    """The submission interface: tickets of mixed orders under a budget that defers
+    admission return the same fields as each solve run alone, plus its energies."""
+    cases = [(2, 3, 11, 30), (3, 5, 12, 17), (2, 8, 13, 9)]
+    dt = 1e-3
+    sch = serve.Scheduler(hbm_budget_bytes=2 * 2 ** 20, steps_per_launch=8)
+    tickets, alone = [], []
+    for (n, p, seed, steps) in cases:
+        verts, tets, eps, E, H = _case(n, p, seed)
+        tickets.append(sch.submit(verts, tets, p, eps, None, E, H, dt, steps))
+        m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
+        Eg, Hg = torch.tensor(E, device="cuda"), torch.tensor(H, device="cuda")
+        m.step(Eg, Hg, dt, steps)
+        alone.append((Eg, Hg, m.energy(Eg, Hg, dt=dt)))
+    E2, H2, en2, lat2 = tickets[2].result()
+    sch.drain()
+    for t, (Ea, Ha, ena) in zip(tickets, alone):
+        E, H, en, lat = t.result()
+        assert torch.equal(E, Ea) and torch.equal(H, Ha)
+        assert en == ena and lat > 0
+    sch.close()
