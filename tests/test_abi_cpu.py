@@ -62,6 +62,8 @@ def test_mesh_errors_are_reported_before_device_work():
     v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]], float)
     rc, msg = _create(v, [[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]])
     assert rc == -3 and "more than two" in msg
+    rc, msg = _create(flat, np.zeros((0, 4), np.int64))  # empty mesh
+    assert rc == -1
     lib = P.load_library()
     assert lib.dgm_create_mesh(None, 0, None, 0, None) == -1
     assert lib.dgm_set_order(None, 2) == -1
