@@ -223,3 +223,34 @@ def test_estimate_dt_fp32_path_at_p8():
     dt, est = m.estimate_dt(cfl=0.5, iters=150, seed=5)
     print(f"p=8 rho: library {est:.6e}, oracle {est_or:.6e}")
     assert abs(est - est_or) < 1e-2 * est_or
+
+
+def test_config_16cube_p4_fp32_1000_steps():
+    """The 16^3 x 6, p = 4 FP32 workload over its full 1000 steps: the leapfrog invariant Q
+    (checked every 100 steps in FP64) drifts by less than 1e-6 relative, and the FP32 run
+    stays within 1e-5 (energy norm) of the FP64 run of the same library, whose operator is
+    pinned to the oracle above (the oracle itself is too slow for 24,576 tets x 1000 steps)."""
+    from paper_1104_4208_amd.project import project_covariant
+
+    w = synth.WORKLOADS["cube16_p4_f32"]
+    d = synth.build_workload(w)
+    verts, tets = d["verts"], d["tets"]
+    m = P.Mesh(verts, tets).set_order(w.p).set_material(d["eps"], d["mu"])
+    dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
+    E0 = np.ascontiguousarray(project_covariant(verts, tets, w.p, d["field"].E))
+    E32, H32 = dev(E0, torch.float32), torch.zeros((3, P.num_modes(w.p), tets.shape[0]), dtype=torch.float32, device="cuda")
+    E64, H64 = dev(E0, torch.float64), torch.zeros_like(H32, dtype=torch.float64)
+    _, Q0 = m.energy(E32, H32, dt=dt)
+    worst_q = 0.0
+    for blk in range(10):
+        m.step(E32, H32, dt, 100)
+        m.step(E64, H64, dt, 100)
+        _, Q = m.energy(E32, H32, dt=dt)
+        worst_q = max(worst_q, abs(Q - Q0) / Q0)
+    dE, dH = E32.double() - E64, H32.double() - H64
+    num, _ = m.energy(dE.contiguous(), dH.contiguous())
+    den, _ = m.energy(E64, H64)
+    err = math.sqrt(num / den)
+    print(f"16^3 p4 1000 steps: Q drift {worst_q:.2e}, FP32 vs FP64 {err:.2e}")
+    assert worst_q < 1e-6
+    assert err < 1e-5
