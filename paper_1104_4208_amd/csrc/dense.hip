@@ -62,17 +62,20 @@ __device__ __forceinline__ void gemm_acc(const T* __restrict__ A, int KP, const 
   const int half = l >> 5, r = l & 31;
   acc0 = f32x16{};
   acc1 = f32x16{};
-  const T* arow = A + (size_t)(rt * 32 + r) * KP + half * 8;
+  // the operator is stored in fragment order (frag_order): the 64 lanes' fragments of
+  // one row tile and k-step are one contiguous 1 KB block
+  const V8* af = reinterpret_cast<const V8*>(A) + (size_t)rt * (KP / 16) * 64 + l;
   const T* b0 = Bs + (size_t)r * (KP + kPad) + half * 8;
   const T* b1 = Bs + (size_t)(32 + r) * (KP + kPad) + half * 8;
   // operator fragments are fetched (from L2) three k-steps ahead
-  const int last = KP - 16;
-  V8 a0 = *reinterpret_cast<const V8*>(arow);
-  V8 a1 = *reinterpret_cast<const V8*>(arow + (16 < last ? 16 : last));
-  V8 a2 = *reinterpret_cast<const V8*>(arow + (32 < last ? 32 : last));
+  const int last = KP / 16 - 1;
+  V8 a0 = af[0];
+  V8 a1 = af[(1 < last ? 1 : last) * 64];
+  V8 a2 = af[(2 < last ? 2 : last) * 64];
 #pragma unroll 4
   for (int ks = 0; ks < KP; ks += 16) {
-    const V8 a3 = *reinterpret_cast<const V8*>(arow + (ks + 48 < last ? ks + 48 : last));
+    const int s3 = ks / 16 + 3;
+    const V8 a3 = af[(s3 < last ? s3 : last) * 64];
     const V8 x0 = *reinterpret_cast<const V8*>(b0 + ks);
     const V8 x1 = *reinterpret_cast<const V8*>(b1 + ks);
     acc0 = mfma(a0, x0, acc0);
@@ -286,7 +289,19 @@ int dense_build(int p, int prec, DenseOps** out, const char** err) {
       AU[(size_t)(k * N + s.r) * KP2 + i * N + s.c] -= s.v;
     }
   }
-  auto conv = [&](const std::vector<double>& src, void** dst) -> int {
+  // fragment order: block (row tile rt, k-step s) holds, for lane l, the 8 values of
+  // row rt*32 + l%32 at columns s*16 + (l/32)*8 .. +7 (the MFMA A-operand layout)
+  auto frag_order = [](const std::vector<double>& a, int rows, int KP) {
+    std::vector<double> o(a.size());
+    size_t q = 0;
+    for (int rt = 0; rt < rows / 32; ++rt)
+      for (int s = 0; s < KP / 16; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int i = 0; i < 8; ++i) o[q++] = a[(size_t)(rt * 32 + l % 32) * KP + s * 16 + (l / 32) * 8 + i];
+    return o;
+  };
+  auto conv = [&](const std::vector<double>& rowmajor, int rows, int KP, void** dst) -> int {
+    const std::vector<double> src = frag_order(rowmajor, rows, KP);
     std::vector<uint16_t> h(src.size());
     for (size_t q = 0; q < src.size(); ++q) h[q] = prec == 0 ? to_bf16(src[q]) : to_f16(src[q]);
     if (hipMalloc(dst, h.size() * 2) != hipSuccess) return -5;
@@ -300,8 +315,8 @@ int dense_build(int p, int prec, DenseOps** out, const char** err) {
   d->NF = NF;
   d->KP1 = KP1;
   d->KP2 = KP2;
-  int rc = conv(AT, &d->AT);
-  if (!rc) rc = conv(AU, &d->AU);
+  int rc = conv(AT, M1P, KP1, &d->AT);
+  if (!rc) rc = conv(AU, M3P, KP2, &d->AU);
   if (rc) {
     dense_free(d);
     *err = "device allocation for the dense operators failed";
