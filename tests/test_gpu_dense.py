@@ -35,7 +35,7 @@ def host(t):
 
 
 @pytest.mark.parametrize("prec", [P.DGM_BF16, P.DGM_F16])
-@pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_dense_apply_curl_parity(p, prec):
     rng = np.random.default_rng(200 + p)
     verts, tets = synth.kuhn_mesh(2, 0.1, rng)
