@@ -115,6 +115,16 @@ int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void
  * multiple of 64, times 8 x the padded face-mode count, values of dtype each). */
 int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
 
+/* dgm_step that also records, after each step n (0-based), signal[n] = sum_i w_i S_i,
+ * a fixed linear functional of E: S are the library's internal coefficients of E
+ * during the run (covariant coefficients mapped by the per-element mass inverse and
+ * the derivative frame) and w is a device array of E's shape and dtype.  A generic w
+ * (e.g. random) sees every mode, which is what a frequency analysis of the time
+ * signal needs (the resonance workload of Section 2.2's numerical example).
+ * signal: host array of nsteps doubles; synchronises the stream. */
+int dgm_step_probe(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, const void* w,
+                   double* signal, hipStream_t stream);
+
 /* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),
  * out[1] = Q = 1/2 (E, M_eps E) + 1/2 (H, M_mu H_next), the quantity the
  * H-first symplectic Euler step conserves exactly.  H_next is the H of the next

@@ -142,6 +142,23 @@ __global__ void __launch_bounds__(kRedThreads) final_sum_kernel(const double* __
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Partial sums (FP64) of the plain dot product of two arrays; one per block.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) dot_partial_kernel(const R* __restrict__ A, const R* __restrict__ B,
+                                                                  size_t n, double* __restrict__ partial) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads)
+    acc += (double)A[i] * (double)B[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014) mapped to [-1, 1): start vector of the
 // power iteration, identical to the host reference generator.
 template <typename R>
@@ -406,10 +423,27 @@ int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s) {
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
 
+constexpr int kDotBlocks = 512;
+
+int ensure_partial(dgm_mesh* m, int nb) {
+  if (m->partial_n >= nb) return DGM_OK;
+  if (m->d_partial) HIP_TRY(hipFree(m->d_partial));
+  m->d_partial = nullptr;
+  m->partial_n = 0;
+  HIP_TRY(hipMalloc(&m->d_partial, nb * sizeof(double)));
+  m->partial_n = nb;
+  return DGM_OK;
+}
+
+// With w and d_sig: after step n, d_sig[n] = sum_i w_i E_i (E in the stored frame).
 template <typename R>
-int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s) {
+int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s, const R* w = nullptr,
+              double* d_sig = nullptr) {
   int rc;
   if (nsteps == 0) return DGM_OK;
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  const int nb = (int)std::min<size_t>(kDotBlocks, (n + kRedThreads - 1) / kRedThreads);
+  if (w && (rc = ensure_partial(m, nb))) return rc;
   R *TE, *TH;
   if ((rc = ensure_traces<R>(m, &TE, &TH))) return rc;
   if ((rc = convert<R>(m, E, 0, true, s))) return rc;
@@ -420,6 +454,12 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s)
     // (writes the traces of E for the next step, except after the last one)
     if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s))) return rc;
     if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s))) return rc;
+    if (w) {
+      hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, (const R*)E, w, n, m->d_partial);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_sig + it);
+      HIP_TRY(hipGetLastError());
+    }
   }
   if ((rc = convert<R>(m, E, 0, false, s))) return rc;
   return convert<R>(m, H, 1, false, s);
@@ -428,12 +468,8 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s)
 template <typename R>
 int mdot(dgm_mesh* m, const R* A, const R* B, int fld, double* d_out, hipStream_t s) {
   const int nb = (int)((m->K + kRedThreads - 1) / kRedThreads);
-  if (m->partial_n < nb) {
-    if (m->d_partial) HIP_TRY(hipFree(m->d_partial));
-    m->d_partial = nullptr;
-    HIP_TRY(hipMalloc(&m->d_partial, nb * sizeof(double)));
-    m->partial_n = nb;
-  }
+  int rc;
+  if ((rc = ensure_partial(m, nb))) return rc;
   hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, A, B, m->d_G[fld], num_modes(m->p),
                      (int)m->K, m->d_partial);
   HIP_TRY(hipGetLastError());
@@ -742,6 +778,25 @@ int dgm_step(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps
   if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
   return dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s)
                           : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s);
+}
+
+int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps, const void* w,
+                   double* signal, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if (!E || !H || E == H || !w || !signal || nsteps < 0 || !std::isfinite(dt))
+    return fail(DGM_ERR_ARG, "bad step_probe arguments");
+  if (nsteps == 0) return DGM_OK;
+  double* d_sig = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&d_sig), (size_t)nsteps * sizeof(double), s));
+  rc = dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, (const float*)w, d_sig)
+                        : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, (const double*)w, d_sig);
+  if (!rc) {
+    HIP_TRY(hipMemcpyAsync(signal, d_sig, (size_t)nsteps * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipFreeAsync(d_sig, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return rc;
 }
 
 int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void* Hn, double dt, double out[2],

@@ -46,6 +46,7 @@ SIGNATURES = {
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
     "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
+    "dgm_step_probe": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p, _pd, _c_p]),
     "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
     "dgm_apply_curl_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
@@ -220,6 +221,19 @@ class Mesh:
             raise DGMError("E and H must share a dtype")
         _check(load_library().dgm_step(self._h, _dtype_code(E), _ptr(E), _ptr(H), float(dt), int(nsteps), _stream()))
         return E, H
+
+    def step_probe(self, E, H, dt: float, nsteps: int, w):
+        """nsteps steps in place; returns the FP64 signal w . S(E) after every step
+        (numpy array of nsteps values; see dgm_step_probe)."""
+        E, H, w = self._field(E, "E"), self._field(H, "H"), self._field(w, "w")
+        if not (E.dtype == H.dtype == w.dtype):
+            raise DGMError("E, H and w must share a dtype")
+        sig = (ctypes.c_double * max(int(nsteps), 1))()
+        _check(load_library().dgm_step_probe(self._h, _dtype_code(E), _ptr(E), _ptr(H), float(dt), int(nsteps),
+                                             _ptr(w), sig, _stream()))
+        import numpy as np
+
+        return np.array(sig[:int(nsteps)], dtype=np.float64)
 
     def energy(self, E, H, H_next=None, dt: float = 0.0):
         """(W, Q) in FP64; Q uses H_next (computed as H + dt dH(E) when None)."""
