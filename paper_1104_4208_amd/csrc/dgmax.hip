@@ -200,6 +200,7 @@ struct dgm_mesh {
   size_t T_bytes = 0;
   double* d_partial = nullptr;
   int partial_n = 0;
+  double* d_res = nullptr;  // four FP64 reduction results (energies)
   // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
   DenseOps* dense[2] = {nullptr, nullptr};
   float* d_jump = nullptr;
@@ -482,8 +483,8 @@ template <typename R>
 int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, double out[2], hipStream_t s) {
   const size_t n = (size_t)3 * num_modes(m->p) * m->K;
   int rc;
-  double* d_res = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&d_res), 4 * sizeof(double), s));
+  if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
+  double* d_res = m->d_res;
   const R* Hq = Hn;
   R* hn_buf = nullptr;
   if (!Hq) {
@@ -502,7 +503,6 @@ int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, dou
   if ((rc = mdot<R>(m, H, Hq, 1, d_res + 2, s))) return rc;
   double h[4];
   HIP_TRY(hipMemcpyAsync(h, d_res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipFreeAsync(d_res, s));
   HIP_TRY(hipStreamSynchronize(s));
   out[0] = 0.5 * h[0] + 0.5 * h[1];
   out[1] = 0.5 * h[0] + 0.5 * h[2];
@@ -562,7 +562,7 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
   const int threads = 256;
   const unsigned blocks = (unsigned)((n + threads - 1) / threads);
   hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(threads), 0, s, x, n, (unsigned long long)seed);
-  HIP_TRY(hipGetLastError());
+  if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "start vector kernel launch failed");
   for (int it = 0; it < iters && !rc; ++it) {
     // z = dH(dE(x)) = -B x, where B = M_mu^{-1} C M_eps^{-1} C^T is similar to the
     // symmetric matrix of the bound; Rayleigh quotient in the M_mu inner product
@@ -576,12 +576,14 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
     std::swap(x, z);
   }
   double h[3] = {0, 0, 0};
-  if (!rc) {
-    HIP_TRY(hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipFreeAsync(base, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(base, s);  // freed on every path
+  const hipError_t e3 = hipStreamSynchronize(s);
   if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
   const double rho = -h[0] / h[1];
   if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
   if (rho_out) *rho_out = rho;
@@ -726,6 +728,7 @@ int dgm_destroy(dgm_mesh* m) {
   hipFree(m->d_scratch);
   hipFree(m->d_T);
   hipFree(m->d_partial);
+  hipFree(m->d_res);
   dense_free(m->dense[0]);
   dense_free(m->dense[1]);
   hipFree(m->d_jump);
@@ -791,12 +794,15 @@ int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t 
   HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&d_sig), (size_t)nsteps * sizeof(double), s));
   rc = dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, (const float*)w, d_sig)
                         : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, (const double*)w, d_sig);
-  if (!rc) {
-    HIP_TRY(hipMemcpyAsync(signal, d_sig, (size_t)nsteps * sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipFreeAsync(d_sig, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return rc;
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(signal, d_sig, (size_t)nsteps * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(d_sig, s);  // freed on every path
+  const hipError_t e3 = hipStreamSynchronize(s);
+  if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
+  return DGM_OK;
 }
 
 int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void* Hn, double dt, double out[2],
