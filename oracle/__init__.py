@@ -2,7 +2,7 @@
 Maxwell solver, written from the paper's statement of the method.
 
 THIS PACKAGE IS TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()``
-and the ``cpu_baseline`` leg of ``bench.py`` may import it.  The product
+and the ``cpu_baseline`` leg of ``bench.py`` (``oracle_leg``) may import it.  The product
 (``paper_1104_4208_amd``) never imports or calls it, and it shares no code
 with the product: its Jacobi polynomials, quadrature, basis, geometry,
 neighbour search and operators are written here independently.
@@ -14,7 +14,7 @@ Contents
              right-hand sides, symplectic Euler (Section 3), energies, power
              iteration for the time-step bound, dense operator assembly.
 
-Pins (tests/test_oracle_*.py) tie each function to something other than
+Pins (tests/test_oracle.py) tie each function to something other than
 itself: closed-form norms, orthogonality, integration by parts, exact
 polynomial reproduction of curl, skew-symmetry of the semi-discrete system,
 exact conservation of the leapfrog invariant, the scalar stability
