@@ -77,7 +77,7 @@ int dgm_mode_index(int p, int m, int* i, int* j, int* k);
  * (vertex ids in [0, nv)).  Vertices of each tetrahedron are sorted by
  * ascending id, so both sides of a face parametrise it identically; the
  * neighbour map is built from shared vertex triples (Section 3, locality of
- * the DG curl).  nt >= 1 (an empty mesh is DGM_ERR_ARG).  Errors: DGM_ERR_ARG, DGM_ERR_MESH_DEGENERATE,
+ * the DG curl).  1 <= nt <= 2^28 - 64 (an empty mesh is DGM_ERR_ARG).  Errors: DGM_ERR_ARG, DGM_ERR_MESH_DEGENERATE,
  * DGM_ERR_MESH_NONMANIFOLD, DGM_ERR_OOM, DGM_ERR_HIP.  Material defaults to
  * eps = mu = 1 and the order must be set before any field operation. */
 int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_t nt, dgm_mesh** out);

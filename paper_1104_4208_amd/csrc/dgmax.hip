@@ -44,6 +44,8 @@ int fail(int code, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                   \
   } while (0)
 
+constexpr int64_t kMaxElements = (int64_t(1) << 28) - 64;
+
 int num_modes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 int num_face_modes(int p) { return (p + 1) * (p + 2) / 2; }
 // Values of one field's trace buffer: whole 64-element tiles (the last one padded).
@@ -81,17 +83,24 @@ __global__ void convert_kernel(R* __restrict__ X, const R* __restrict__ Msym, in
   }
 }
 
+// Elementwise kernels over whole fields (3 N K values, which can exceed the 2^32
+// work-items of one launch) loop with a grid stride over a capped grid.
+constexpr int kFlatThreads = 256;
+constexpr size_t kFlatMaxBlocks = 65536;
+inline unsigned flat_blocks(size_t n) {
+  return (unsigned)std::min<size_t>(kFlatMaxBlocks, std::max<size_t>(1, (n + kFlatThreads - 1) / kFlatThreads));
+}
+
 template <typename R>
 __global__ void fill_kernel(R* __restrict__ X, size_t n, R v) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) X[i] = v;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) X[i] = v;
 }
 
 // Y <- X + a * Y  (used to form H_next = H + dt dH in place of dH)
 template <typename R>
 __global__ void xpay_kernel(R* __restrict__ Y, const R* __restrict__ X, size_t n, double a) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) Y[i] = (R)((double)X[i] + a * (double)Y[i]);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    Y[i] = (R)((double)X[i] + a * (double)Y[i]);
 }
 
 // Mass-weighted dot products in FP64: out[b] = sum over the block's elements of
@@ -163,19 +172,20 @@ __global__ void __launch_bounds__(kRedThreads) dot_partial_kernel(const R* __res
 // power iteration, identical to the host reference generator.
 template <typename R>
 __global__ void splitmix_fill_kernel(R* __restrict__ X, size_t n, unsigned long long seed) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z = z ^ (z >> 31);
-  X[i] = (R)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    X[i] = (R)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  }
 }
 
 template <typename R>
 __global__ void scale_kernel(R* __restrict__ X, size_t n, const double* __restrict__ d) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) X[i] = (R)(-(double)X[i] / sqrt(*d));
+  const double r = sqrt(*d);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    X[i] = (R)(-(double)X[i] / r);
 }
 
 }  // namespace
@@ -365,8 +375,7 @@ int convert(dgm_mesh* m, R* X, int fld, bool to_stored, hipStream_t s) {
 
 template <typename R>
 int fill(R* X, size_t n, R v, hipStream_t s) {
-  const int threads = 256;
-  hipLaunchKernelGGL(fill_kernel<R>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, X, n, v);
+  hipLaunchKernelGGL(fill_kernel<R>, dim3(flat_blocks(n)), dim3(kFlatThreads), 0, s, X, n, v);
   HIP_TRY(hipGetLastError());
   return DGM_OK;
 }
@@ -492,9 +501,7 @@ int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, dou
     if ((rc = ensure_scratch(m, 2 * n * sizeof(R)))) return rc;
     hn_buf = static_cast<R*>(m->d_scratch) + n;
     if ((rc = rate_impl<R>(m, E, hn_buf, 0, s))) return rc;
-    const int threads = 256;
-    hipLaunchKernelGGL(xpay_kernel<R>, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, hn_buf, H,
-                       n, dt);
+    hipLaunchKernelGGL(xpay_kernel<R>, dim3(flat_blocks(n)), dim3(kFlatThreads), 0, s, hn_buf, H, n, dt);
     HIP_TRY(hipGetLastError());
     Hq = hn_buf;
   }
@@ -559,9 +566,8 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
   R* z = y + n;
   // three FP64 dot products after the vectors, aligned to 8 bytes
   double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(z + n) + 7) & ~uintptr_t(7));
-  const int threads = 256;
-  const unsigned blocks = (unsigned)((n + threads - 1) / threads);
-  hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(threads), 0, s, x, n, (unsigned long long)seed);
+  const unsigned blocks = flat_blocks(n);
+  hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, x, n, (unsigned long long)seed);
   if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "start vector kernel launch failed");
   for (int it = 0; it < iters && !rc; ++it) {
     // z = dH(dE(x)) = -B x, where B = M_mu^{-1} C M_eps^{-1} C^T is similar to the
@@ -571,7 +577,7 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
     if ((rc = mdot<R>(m, x, z, 1, d + 0, s))) break;
     if ((rc = mdot<R>(m, x, x, 1, d + 1, s))) break;
     if ((rc = mdot<R>(m, z, z, 1, d + 2, s))) break;
-    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(threads), 0, s, z, n, d + 2);
+    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, z, n, d + 2);
     if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
     std::swap(x, z);
   }
@@ -619,7 +625,9 @@ int dgm_mode_index(int p, int m, int* i, int* j, int* k) {
 
 int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_t nt, dgm_mesh** out) {
   if (!verts || !tets || !out || nv < 4 || nt < 1) return fail(DGM_ERR_ARG, "bad mesh arguments");
-  if (nt > (int64_t(1) << 28)) return fail(DGM_ERR_ARG, "too many elements");
+  // neighbour codes 4 e + f stay in int32, and a per-tile launch of up to 1024
+  // threads per 64 elements stays below 2^32 work-items
+  if (nt > kMaxElements) return fail(DGM_ERR_ARG, "too many elements (max " + std::to_string(kMaxElements) + ")");
   *out = nullptr;
   auto* m = new dgm_mesh();
   m->K = nt;

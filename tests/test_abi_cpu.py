@@ -65,6 +65,13 @@ def test_mesh_errors_are_reported_before_device_work():
     rc, msg = _create(flat, np.zeros((0, 4), np.int64))  # empty mesh
     assert rc == -1
     lib = P.load_library()
+    # the element-count limit is checked before the arrays are read
+    v = np.ascontiguousarray(v)
+    t = np.zeros((1, 4), np.int64)
+    h = ctypes.c_void_p()
+    rc = lib.dgm_create_mesh(v.ctypes.data_as(D._pd), v.shape[0], t.ctypes.data_as(D._pi64), (1 << 28) - 63,
+                             ctypes.byref(h))
+    assert rc == -1 and "too many elements" in lib.dgm_last_error().decode()
     assert lib.dgm_create_mesh(None, 0, None, 0, None) == -1
     assert lib.dgm_set_order(None, 2) == -1
     assert lib.dgm_step(None, 0, None, None, 0.1, 1, None) == -1
