@@ -50,6 +50,12 @@ int num_modes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 int num_face_modes(int p) { return (p + 1) * (p + 2) / 2; }
 // Values of one field's trace buffer: whole 64-element tiles (the last one padded).
 size_t trace_words(int64_t K, int p) { return (size_t)((K + 63) / 64) * 64 * trace_elem_stride(num_face_modes(p)); }
+// Bytes a leapfrog step streams through (both fields and both trace buffers); above
+// the 256 MB last-level cache the phase kernels use nontemporal field accesses.
+constexpr size_t kStreamingBytes = size_t(256) << 20;
+size_t step_bytes(int64_t K, int p, size_t rsize) {
+  return (2 * (size_t)3 * num_modes(p) * (size_t)K + 2 * trace_words(K, p)) * rsize;
+}
 
 // ---------------------------------------------------------------- kernels
 // X_m <- P X_m for every mode m of every element, P = (Minv A) (to the stored
@@ -410,6 +416,7 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
   a.wall = fld_u == 0 ? (R)-1 : (R)1;
   a.K = (int)m->K;
   a.blocks = (int)((m->K + 63) / 64);
+  a.streaming = step_bytes(m->K, m->p, sizeof(R)) > kStreamingBytes;
   a.stream = s;
   HIP_TRY(phase(a, m->p));
   return DGM_OK;
@@ -902,6 +909,7 @@ struct dgm_batch {
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
   unsigned live_orders = 0;  // orders with active slots in the captured graph
+  int streaming = 0;         // nontemporal field accesses (working set of all slots above the cache)
 };
 
 namespace {
@@ -925,6 +933,7 @@ int batch_capture(dgm_batch* b) {
         a.phase = phase;
         a.substep = sub;
         a.blocks = b->cap_tiles[p];
+        a.streaming = b->streaming;
         a.stream = b->cap_stream;
         err = kBatchF32[p](a);
       }
@@ -1046,6 +1055,13 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
     if (!b->h_slots[p].empty()) live |= 1u << p;
   if (live != b->live_orders) {
     b->live_orders = live;
+    b->dirty = true;
+  }
+  size_t bytes = 0;
+  for (const auto& q : b->active) bytes += step_bytes(q.m->K, q.m->p, sizeof(float));
+  const int streaming = bytes > kStreamingBytes;
+  if (streaming != b->streaming) {
+    b->streaming = streaming;
     b->dirty = true;
   }
   int rc;

@@ -321,7 +321,7 @@ def _trace_job(a_, t, g, f, rows, ind):
         for k in range(2):
             vals = [f"ts{k}_{m}" if m in rows else "R(0)" for m in range(4 * mq, 4 * mq + 4)]
             chunk = f * FQ + (k * NFP + 4 * mq) // 4
-            a_(ind + f"  store4(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
+            a_(ind + f"  store4s<ST>(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
     a_(ind + "}")
 
 
@@ -370,7 +370,7 @@ def _lift_job(a_, t, Lp, rows, ind):
     if early:
         a_(ind + "  // old values of the updated rows")
         for j, b in enumerate(rows):
-            a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = V[({k * N + b}) * Ks + el]" for k in range(3)) + ";")
+            a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = ldf<ST>(&V[({k * N + b}) * Ks + el])" for k in range(3)) + ";")
     jd = lambda f, k, m: f"wl[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
     for f in range(4):
         ks = [k for k in range(3) if np.any(Lp[f][k] != 0)]
@@ -422,12 +422,12 @@ def _lift_job(a_, t, Lp, rows, ind):
     # the new values stay in the accumulator slots (the traces of V are formed from them)
     for j, b in enumerate(rows):
         for k in range(3):
-            old = f"vo{k}_{j}" if early else f"V[({k * N + b}) * Ks + el]"
+            old = f"vo{k}_{j}" if early else f"ldf<ST>(&V[({k * N + b}) * Ks + el])"
             a_(ind + f"  acc{k}_{j} = {old} + sdt * acc{k}_{j};")
     a_(ind + "  if (act) {")
     for j, b in enumerate(rows):
         for k in range(3):
-            a_(ind + f"    V[({k * N + b}) * Ks + e] = acc{k}_{j};")
+            a_(ind + f"    stf<ST>(&V[({k * N + b}) * Ks + e], acc{k}_{j});")
     a_(ind + "  }")
     a_(ind + "}")
 
@@ -475,8 +475,9 @@ def _stage_parts(t, nw, X, mp):
     for i in range(cnt):
         idx = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {N - 1})"
         ld.append(f"const int a{i} = {idx};")
-        ld.append(f"const R s{i}_0 = {X}[(size_t)a{i} * Ks + ez], s{i}_1 = {X}[(size_t)({N} + a{i}) * Ks + ez], "
-                  f"s{i}_2 = {X}[(size_t)({2 * N} + a{i}) * Ks + ez];")
+        ld.append(f"const R s{i}_0 = ldf<ST>(&{X}[(size_t)a{i} * Ks + ez]), "
+                  f"s{i}_1 = ldf<ST>(&{X}[(size_t)({N} + a{i}) * Ks + ez]), "
+                  f"s{i}_2 = ldf<ST>(&{X}[(size_t)({2 * N} + a{i}) * Ks + ez]);")
         st.append(f"wl[a{i} * {LANES} + lz] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
         st.append(f"wl[({N} + a{i}) * {LANES} + lz] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
         st.append(f"wl[({2 * N} + a{i}) * {LANES} + lz] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
@@ -646,7 +647,8 @@ def emit_phase(p: int) -> str:
     L = []
     a_ = L.append
     _header(a_, p, t, nw, pl, "single-mesh phase")
-    a_("template <typename R>")
+    a_("// ST: field loads and stores and trace stores carry the nontemporal hint (launch.h)")
+    a_("template <typename R, bool ST>")
     a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
     a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K)")
@@ -670,6 +672,7 @@ def emit_trace(p: int) -> str:
     a_(f"__global__ void {_launch_bounds(p, nw)} dgm_trace_p{p}(const R* __restrict__ U,")
     a_("    const R* __restrict__ MU, R* __restrict__ Tout, int K)")
     a_("{")
+    a_("  constexpr bool ST = false;")
     a_(f"  __shared__ R wl[{lds_words(p)}];")
     _tile_prologue(a_)
     _elem_prologue(a_)
@@ -689,7 +692,7 @@ def emit_batch(p: int) -> str:
     a_("// One launch advances every slot (mesh) of this order.  Block b belongs to the last")
     a_("// slot s with tile0[s] <= b; blocks past the table, or of slots whose remaining")
     a_("// steps are exhausted at this sub-step, exit before any barrier.")
-    a_("template <typename R>")
+    a_("template <typename R, bool ST>")
     a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_batch_p{p}(const BatchSlot* __restrict__ slots,")
     a_("    const int* __restrict__ tile0, const int* __restrict__ nslots, int phase, int substep)")
     a_("{")
@@ -743,7 +746,10 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f'#include "phase_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_p{p}(const PhaseArgs<R>& a) {{",
-              f"  hipLaunchKernelGGL(dgm_phase_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
+              "  if (a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
+              "  else",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
               "  return hipGetLastError();",
               "}",
               f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]
@@ -769,7 +775,10 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               '#include "../launch.h"',
               f'#include "batch_p{p}.inc"',
               f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a) {{",
-              f"  hipLaunchKernelGGL(dgm_phase_batch_p{p}<float>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
+              "  if (a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_batch_p{p}<float, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
+              "  else",
+              f"    hipLaunchKernelGGL((dgm_phase_batch_p{p}<float, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.slots, a.tile0, a.nslots, a.phase, a.substep);",
               "  return hipGetLastError();",
               "}"]
         units.append(_write_if_changed(os.path.join(outdir, f"batch_p{p}.hip"), "\n".join(tb) + "\n"))
