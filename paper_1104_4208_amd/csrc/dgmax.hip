@@ -203,7 +203,10 @@ struct dgm_mesh {
   std::vector<double> F;   // (K,9) row-major 3x3, columns v1-v0, v2-v0, v3-v0 (sorted vertices)
   std::vector<double> J;   // signed det F
   std::vector<int> nbr;    // (4,K)
-  // device
+  // device: one block (d_geom) holds the neighbour codes and every per-element factor;
+  // the pointers below point into it and are never freed on their own
+  void* d_geom = nullptr;
+  size_t geom_off[12] = {};                  // byte offsets of the arrays, see geom_layout
   int* d_nbr = nullptr;
   float* d_M32[2] = {nullptr, nullptr};      // E, H: w = M S
   double* d_M64[2] = {nullptr, nullptr};
@@ -274,19 +277,46 @@ bool inv3(const double a[3][3], double r[3][3]) {
   return true;
 }
 
-template <typename T>
-int upload(T** dst, const std::vector<T>& src) {
-  if (!*dst) HIP_TRY(hipMalloc(dst, src.size() * sizeof(T)));
-  HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-  return DGM_OK;
+// Arrays of the per-mesh device block, in order; the material-dependent ones follow the
+// neighbour codes contiguously so that one copy uploads them.  A device allocation costs
+// about as much as a small mesh's whole set-up, hence one block instead of eleven.
+enum GeomArray { kNbr, kM32E, kM32H, kMinv32E, kMinv32H, kM64E, kM64H, kMinv64E, kMinv64H, kGE, kGH, kGeomArrays };
+static_assert(sizeof(dgm_mesh::geom_off) == (kGeomArrays + 1) * sizeof(size_t), "one offset per array plus the total");
+
+// Byte offsets (256-byte aligned) of the arrays for K elements; off[kGeomArrays] = total.
+void geom_layout(int64_t K, size_t off[kGeomArrays + 1]) {
+  const size_t k6 = 6 * (size_t)K;
+  const size_t sz[kGeomArrays] = {4 * (size_t)K * sizeof(int), k6 * sizeof(float), k6 * sizeof(float),
+                                  k6 * sizeof(float), k6 * sizeof(float), k6 * sizeof(double), k6 * sizeof(double),
+                                  k6 * sizeof(double), k6 * sizeof(double), k6 * sizeof(double), k6 * sizeof(double)};
+  size_t o = 0;
+  for (int i = 0; i < kGeomArrays; ++i) {
+    off[i] = o;
+    o += (sz[i] + 255) & ~size_t(255);
+  }
+  off[kGeomArrays] = o;
 }
+
 
 int material_impl(dgm_mesh* m, const double* eps, const double* mu) {
   const int64_t K = m->K;
   const double(*A)[3] = reinterpret_cast<const double(*)[3]>(kFrameA);
+  // host image of the material part of the device block: every value is checked and
+  // computed before the one upload, so a rejected material leaves the mesh unchanged
+  const size_t* off = m->geom_off;
+  std::vector<unsigned char> img(off[kGeomArrays] - off[kM32E]);
+  const auto at = [&](int arr) { return img.data() + (off[arr] - off[kM32E]); };
+  for (int arr = kM32E; arr < kGeomArrays; ++arr) {  // zero the alignment padding
+    const size_t used = 6 * (size_t)K * (arr < kM64E ? sizeof(float) : sizeof(double));
+    std::memset(at(arr) + used, 0, off[arr + 1] - off[arr] - used);
+  }
   for (int fld = 0; fld < 2; ++fld) {
     const double* mat = fld == 0 ? eps : mu;
-    std::vector<double> M64(6 * K), Minv64(6 * K), G(6 * K);
+    float* M32 = reinterpret_cast<float*>(at(kM32E + fld));
+    float* Minv32 = reinterpret_cast<float*>(at(kMinv32E + fld));
+    double* M64 = reinterpret_cast<double*>(at(kM64E + fld));
+    double* Minv64 = reinterpret_cast<double*>(at(kMinv64E + fld));
+    double* G = reinterpret_cast<double*>(at(kGE + fld));
     for (int64_t e = 0; e < K; ++e) {
       const double c = mat ? mat[e] : 1.0;
       if (!(c > 0.0) || !std::isfinite(c))
@@ -326,21 +356,16 @@ int material_impl(dgm_mesh* m, const double* eps, const double* mu) {
       if (!inv3(Mm, Mi)) return fail(DGM_ERR_MESH_DEGENERATE, "singular element metric");
       double o6[6];
       sym6(Mm, o6);
-      for (int q = 0; q < 6; ++q) M64[q * K + e] = o6[q];
+      for (int q = 0; q < 6; ++q) M64[q * K + e] = o6[q], M32[q * K + e] = (float)o6[q];
       sym6(Mi, o6);
-      for (int q = 0; q < 6; ++q) Minv64[q * K + e] = o6[q];
+      for (int q = 0; q < 6; ++q) Minv64[q * K + e] = o6[q], Minv32[q * K + e] = (float)o6[q];
       sym6(FiFiT, o6);
       for (int q = 0; q < 6; ++q) G[q * K + e] = o6[q];
       (void)FtF;
     }
-    std::vector<float> M32(M64.begin(), M64.end()), Minv32(Minv64.begin(), Minv64.end());
-    int rc;
-    if ((rc = upload(&m->d_M64[fld], M64))) return rc;
-    if ((rc = upload(&m->d_Minv64[fld], Minv64))) return rc;
-    if ((rc = upload(&m->d_M32[fld], M32))) return rc;
-    if ((rc = upload(&m->d_Minv32[fld], Minv32))) return rc;
-    if ((rc = upload(&m->d_G[fld], G))) return rc;
   }
+  HIP_TRY(hipMemcpy(static_cast<unsigned char*>(m->d_geom) + off[kM32E], img.data(), img.size(),
+                    hipMemcpyHostToDevice));
   return DGM_OK;
 }
 
@@ -685,22 +710,34 @@ int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_
     int64_t e;
     int f;
   };
-  std::vector<FaceRec> faces;
-  faces.reserve(4 * nt);
+  std::vector<FaceRec> recs;
+  recs.reserve(4 * nt);
   for (int64_t e = 0; e < nt; ++e)
     for (int f = 0; f < 4; ++f) {
       int64_t id[3];
       int q = 0;
       for (int v = 0; v < 4; ++v)
         if (v != f) id[q++] = sorted[4 * e + v];
-      faces.push_back({id[0], id[1], id[2], e, f});
+      recs.push_back({id[0], id[1], id[2], e, f});
     }
-  std::sort(faces.begin(), faces.end(), [](const FaceRec& x, const FaceRec& y) {
-    if (x.a != y.a) return x.a < y.a;
-    if (x.b != y.b) return x.b < y.b;
-    if (x.c != y.c) return x.c < y.c;
-    return x.e < y.e;
-  });
+  // order by (a, b, c, e): a counting sort on the smallest id a (O(nt + nv)), then each
+  // group sharing a vertex (a few dozen faces) by the other two ids
+  std::vector<int64_t> start(nv + 1, 0);
+  for (const FaceRec& r : recs) ++start[r.a + 1];
+  for (int64_t v = 0; v < nv; ++v) start[v + 1] += start[v];
+  std::vector<FaceRec> faces(recs.size());
+  {
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (const FaceRec& r : recs) faces[pos[r.a]++] = r;
+  }
+  recs = std::vector<FaceRec>();
+  for (int64_t v = 0; v < nv; ++v)
+    if (start[v + 1] - start[v] > 1)
+      std::sort(faces.begin() + start[v], faces.begin() + start[v + 1], [](const FaceRec& x, const FaceRec& y) {
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c != y.c) return x.c < y.c;
+        return x.e < y.e;
+      });
   m->nbr.assign(4 * nt, -1);
   for (size_t s = 0; s < faces.size();) {
     size_t t = s + 1;
@@ -720,7 +757,28 @@ int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_
     }
     s = t;
   }
-  int rc = upload(&m->d_nbr, m->nbr);
+  geom_layout(nt, m->geom_off);
+  const hipError_t ea = hipMalloc(&m->d_geom, m->geom_off[kGeomArrays]);
+  if (ea != hipSuccess) {
+    m->d_geom = nullptr;
+    dgm_destroy(m);
+    return fail(ea == hipErrorOutOfMemory ? DGM_ERR_OOM : DGM_ERR_HIP,
+                std::string("hipMalloc (mesh block): ") + hipGetErrorString(ea));
+  }
+  {
+    unsigned char* base = static_cast<unsigned char*>(m->d_geom);
+    const size_t* off = m->geom_off;
+    m->d_nbr = reinterpret_cast<int*>(base + off[kNbr]);
+    for (int f = 0; f < 2; ++f) {
+      m->d_M32[f] = reinterpret_cast<float*>(base + off[kM32E + f]);
+      m->d_Minv32[f] = reinterpret_cast<float*>(base + off[kMinv32E + f]);
+      m->d_M64[f] = reinterpret_cast<double*>(base + off[kM64E + f]);
+      m->d_Minv64[f] = reinterpret_cast<double*>(base + off[kMinv64E + f]);
+      m->d_G[f] = reinterpret_cast<double*>(base + off[kGE + f]);
+    }
+  }
+  const hipError_t ec = hipMemcpy(m->d_nbr, m->nbr.data(), m->nbr.size() * sizeof(int), hipMemcpyHostToDevice);
+  int rc = ec == hipSuccess ? DGM_OK : fail(DGM_ERR_HIP, std::string("hipMemcpy (neighbours): ") + hipGetErrorString(ec));
   if (!rc) rc = material_impl(m, nullptr, nullptr);
   if (rc) {
     dgm_destroy(m);
@@ -732,14 +790,7 @@ int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_
 
 int dgm_destroy(dgm_mesh* m) {
   if (!m) return DGM_OK;
-  hipFree(m->d_nbr);
-  for (int f = 0; f < 2; ++f) {
-    hipFree(m->d_M32[f]);
-    hipFree(m->d_M64[f]);
-    hipFree(m->d_Minv32[f]);
-    hipFree(m->d_Minv64[f]);
-    hipFree(m->d_G[f]);
-  }
+  hipFree(m->d_geom);  // the neighbour codes and every per-element factor
   hipFree(m->d_scratch);
   hipFree(m->d_T);
   hipFree(m->d_partial);

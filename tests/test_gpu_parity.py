@@ -254,3 +254,25 @@ def test_config_16cube_p4_fp32_1000_steps():
     print(f"16^3 p4 1000 steps: Q drift {worst_q:.2e}, FP32 vs FP64 {err:.2e}")
     assert worst_q < 1e-6
     assert err < 1e-5
+
+
+def test_rejected_material_leaves_mesh_unchanged():
+    """set_material checks every value before it uploads anything: after a call
+    rejected for a bad permeability the operator is still the previous one."""
+    rng = np.random.default_rng(21)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K, N = tets.shape[0], P.num_modes(3)
+    m = P.Mesh(verts, tets).set_order(3).set_material(rng.choice([1.0, 4.0], size=K), rng.uniform(1, 2, K))
+    E = dev(rng.standard_normal((3, N, K)), torch.float64)
+    H = dev(rng.standard_normal((3, N, K)), torch.float64)
+    before = [host(x) for x in m.apply_curl(E, H)]
+    bad_mu = np.ones(K)
+    bad_mu[K - 1] = 0.0
+    with pytest.raises(P.DGMError):
+        m.set_material(np.full(K, 2.0), bad_mu)
+    after = [host(x) for x in m.apply_curl(E, H)]
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    # and a later valid call takes effect
+    m.set_material(np.full(K, 2.0), None)
+    changed = host(m.apply_curl(None, H)[0])
+    assert not np.array_equal(changed, before[0])
