@@ -40,7 +40,7 @@ def device_bytes(K: int, p: int) -> int:
     the per-element geometry the library keeps for the mesh handle."""
     nf = D.num_face_modes(p)
     trace = ((K + 63) // 64) * 64 * 4 * 2 * ((nf + 3) // 4 * 4)
-    return 2 * 3 * D.num_modes(p) * K * 4 + 2 * trace * 4 + K * 260
+    return 2 * 3 * D.num_modes(p) * K * 4 + 2 * trace * 4 + K * 400
 
 
 @dataclass
