@@ -176,7 +176,11 @@ int dgm_batch_destroy(dgm_batch* batch);
 int dgm_batch_add(dgm_batch* batch, dgm_mesh* mesh, float* E, float* H, double dt, int64_t nsteps,
                   hipStream_t stream, int64_t* id);
 int dgm_batch_num_active(const dgm_batch* batch, int64_t* n);
-/* Advances all active slots and synchronises the stream. */
+/* Advances all active slots and synchronises the stream.  When the set of orders
+ * in use, the grid capacity or the cache policy changes, the call first re-captures
+ * its HIP graph; HIP calls made by other threads of the process meanwhile can make
+ * that capture fail (DGM_ERR_HIP), so other threads should not use the GPU during
+ * this call. */
 int dgm_batch_advance(dgm_batch* batch, hipStream_t stream);
 /* Copies up to cap finished slot ids into ids and removes them from the list. */
 int dgm_batch_take_finished(dgm_batch* batch, int64_t* ids, int64_t cap, int64_t* n);
