@@ -222,7 +222,7 @@ def dense_comparison(steps: int):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
