@@ -182,6 +182,17 @@ int dgm_batch_num_active(const dgm_batch* batch, int64_t* n);
  * that capture fail (DGM_ERR_HIP), so other threads should not use the GPU during
  * this call. */
 int dgm_batch_advance(dgm_batch* batch, hipStream_t stream);
+/* dgm_batch_advance in two halves, so the host can work while a chunk runs:
+ * dgm_batch_launch enqueues the chunk (and the retirement of the slots it finishes)
+ * on the stream and returns; dgm_batch_wait synchronises that stream.  Between the
+ * two the caller may set up other meshes but must not launch, take finished ids
+ * (DGM_ERR_STATE) or touch the slots' fields.  If dgm_batch_launch fails after the
+ * graph was launched, dgm_batch_wait is still required. */
+int dgm_batch_launch(dgm_batch* batch, hipStream_t stream);
+int dgm_batch_wait(dgm_batch* batch);
+/* *yes = 1 when the next launch will re-capture its graph (see dgm_batch_advance):
+ * host-only, so a caller can keep other threads off the GPU for just those launches. */
+int dgm_batch_needs_capture(const dgm_batch* batch, int* yes);
 /* Copies up to cap finished slot ids into ids and removes them from the list. */
 int dgm_batch_take_finished(dgm_batch* batch, int64_t* ids, int64_t cap, int64_t* n);
 

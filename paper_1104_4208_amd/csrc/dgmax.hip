@@ -961,6 +961,8 @@ struct dgm_batch {
   bool dirty = true;
   unsigned live_orders = 0;  // orders with active slots in the captured graph
   int streaming = 0;         // nontemporal field accesses (working set of all slots above the cache)
+  bool in_flight = false;    // a chunk was launched and not yet waited for
+  hipStream_t launch_stream = nullptr;
 };
 
 namespace {
@@ -1011,6 +1013,7 @@ int dgm_batch_create(int chunk, dgm_batch** out) {
 
 int dgm_batch_destroy(dgm_batch* b) {
   if (!b) return DGM_OK;
+  if (b->in_flight) (void)hipStreamSynchronize(b->launch_stream);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1052,9 +1055,33 @@ int dgm_batch_num_active(const dgm_batch* b, int64_t* n) {
   return DGM_OK;
 }
 
-int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
-  if (!b) return fail(DGM_ERR_ARG, "null batch");
-  if (b->active.empty()) return DGM_OK;
+}  // extern "C"
+
+namespace {
+
+// Whether the next launch re-captures the graph: the set of orders in use, the slot or
+// tile capacity of an order or the cache policy no longer matches the captured one.
+bool batch_needs_capture(const dgm_batch* b) {
+  if (b->dirty || !b->exec) return true;
+  int ns[DGM_MAX_ORDER_F32 + 1] = {}, nt[DGM_MAX_ORDER_F32 + 1] = {};
+  unsigned live = 0;
+  size_t bytes = 0;
+  for (const auto& q : b->active) {
+    const int p = q.m->p;
+    ++ns[p];
+    nt[p] += (int)((q.m->K + 63) / 64);
+    live |= 1u << p;
+    bytes += step_bytes(q.m->K, p, sizeof(float));
+  }
+  if (live != b->live_orders || (int)(bytes > kStreamingBytes) != b->streaming) return true;
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p)
+    if (ns[p] > b->cap_slots[p] || nt[p] > b->cap_tiles[p]) return true;
+  return false;
+}
+
+// Tables, (re-)capture if needed, graph launch and the retirement of finished slots,
+// all enqueued on s; the caller waits before the tables or the results are used again.
+int batch_launch(dgm_batch* b, hipStream_t s) {
   for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p) {
     b->h_slots[p].clear();
     b->h_tile0[p].assign(1, 0);
@@ -1118,6 +1145,8 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
   int rc;
   if (b->dirty && (rc = batch_capture(b))) return rc;
   HIP_TRY(hipGraphLaunch(b->exec, s));
+  b->in_flight = true;
+  b->launch_stream = s;
   std::vector<dgm_batch::Slot> still;
   for (auto& q : b->active) {
     q.left -= std::min<int64_t>(b->chunk, q.left);
@@ -1130,12 +1159,50 @@ int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
     }
   }
   b->active.swap(still);
-  HIP_TRY(hipStreamSynchronize(s));  // host tables are reused by the next advance
   return DGM_OK;
+}
+
+int batch_wait(dgm_batch* b) {
+  if (!b->in_flight) return DGM_OK;
+  b->in_flight = false;
+  HIP_TRY(hipStreamSynchronize(b->launch_stream));  // host tables are reused by the next launch
+  return DGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgm_batch_needs_capture(const dgm_batch* b, int* yes) {
+  if (!b || !yes) return fail(DGM_ERR_ARG, "null argument");
+  *yes = !b->active.empty() && batch_needs_capture(b);
+  return DGM_OK;
+}
+
+int dgm_batch_launch(dgm_batch* b, hipStream_t s) {
+  if (!b) return fail(DGM_ERR_ARG, "null batch");
+  if (b->in_flight) return fail(DGM_ERR_STATE, "the previous chunk was not waited for (dgm_batch_wait)");
+  if (b->active.empty()) return DGM_OK;
+  return batch_launch(b, s);
+}
+
+int dgm_batch_wait(dgm_batch* b) {
+  if (!b) return fail(DGM_ERR_ARG, "null batch");
+  return batch_wait(b);
+}
+
+int dgm_batch_advance(dgm_batch* b, hipStream_t s) {
+  if (!b) return fail(DGM_ERR_ARG, "null batch");
+  if (b->in_flight) return fail(DGM_ERR_STATE, "the previous chunk was not waited for (dgm_batch_wait)");
+  if (b->active.empty()) return DGM_OK;
+  const int rc = batch_launch(b, s);
+  const int rw = batch_wait(b);
+  return rc ? rc : rw;
 }
 
 int dgm_batch_take_finished(dgm_batch* b, int64_t* ids, int64_t cap, int64_t* n) {
   if (!b || !n || (cap > 0 && !ids)) return fail(DGM_ERR_ARG, "null argument");
+  if (b->in_flight) return fail(DGM_ERR_STATE, "results are ready only after dgm_batch_wait");
   const int64_t k = std::min<int64_t>(cap, (int64_t)b->finished.size());
   for (int64_t q = 0; q < k; ++q) ids[q] = b->finished[q];
   b->finished.erase(b->finished.begin(), b->finished.begin() + k);

@@ -55,6 +55,9 @@ SIGNATURES = {
     "dgm_batch_add": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_d, _c_i64, _c_p, _pi64]),
     "dgm_batch_num_active": (_c_i, [_c_p, _pi64]),
     "dgm_batch_advance": (_c_i, [_c_p, _c_p]),
+    "dgm_batch_launch": (_c_i, [_c_p, _c_p]),
+    "dgm_batch_wait": (_c_i, [_c_p]),
+    "dgm_batch_needs_capture": (_c_i, [_c_p, ctypes.POINTER(_c_i)]),
     "dgm_batch_take_finished": (_c_i, [_c_p, _pi64, _c_i64, _pi64]),
 }
 
@@ -317,6 +320,20 @@ class Batch:
 
     def advance(self):
         _check(load_library().dgm_batch_advance(self._h, _stream()))
+
+    def launch(self):
+        """First half of advance(): enqueue the next chunk and return."""
+        _check(load_library().dgm_batch_launch(self._h, _stream()))
+
+    def wait(self):
+        """Second half of advance(): wait for the launched chunk."""
+        _check(load_library().dgm_batch_wait(self._h))
+
+    def needs_capture(self) -> bool:
+        """Whether the next launch re-captures its HIP graph."""
+        y = _c_i()
+        _check(load_library().dgm_batch_needs_capture(self._h, ctypes.byref(y)))
+        return bool(y.value)
 
     def take_finished(self):
         cap = 4096

@@ -22,10 +22,12 @@ closed-form check.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
 import os
 import sys
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -136,6 +138,22 @@ class Server:
         states = {}
         batch = D.Batch(self.chunk) if mode == "batched" else None
         sid_of = {}
+        if mode == "batched":
+            # Requests are set up (mesh, material, field uploads) on a worker thread while
+            # the GPU runs a chunk on the batch's own stream; the library calls release the
+            # interpreter lock.  A launch that re-captures the batch's graph holds `gate`,
+            # which every set-up holds too, so no other HIP call lands inside a capture.
+            bs = torch.cuda.Stream()
+            prep = cf.ThreadPoolExecutor(max_workers=1)
+            gate = threading.Lock()
+
+            def setup(r):
+                with gate:
+                    out = self._admit(r)
+                    torch.cuda.current_stream().synchronize()  # uploads done before the batch stream reads them
+                    return out
+
+        pending = []  # (request, future of its set-up), in admission order
         t0 = time.perf_counter()
         while len(done) < len(reqs):
             now = time.perf_counter() - t0
@@ -143,21 +161,34 @@ class Server:
                 queue.append(reqs[nxt])
                 nxt += 1
             if mode == "batched":
-                while queue and (used + queue[0].device_bytes() <= self.budget or not live):
+                # reserve memory for what fits (one request always when nothing else holds any)
+                while queue and (used + queue[0].device_bytes() <= self.budget or not (live or pending)):
                     r = queue.pop(0)
-                    m, E, H = self._admit(r)
-                    sid = batch.add(m, E, H, r.dt, r.steps)
+                    used += r.device_bytes()
+                    pending.append((r, prep.submit(setup, r)))
+                # add what is set up; wait for the oldest when the GPU would idle otherwise
+                while pending and (pending[0][1].done() or not live):
+                    r, fut = pending.pop(0)
+                    m, E, H = fut.result()
+                    with torch.cuda.stream(bs):
+                        sid = batch.add(m, E, H, r.dt, r.steps)
                     sid_of[sid] = r.rid
                     live[r.rid] = (r, m, E, H)
-                    used += r.device_bytes()
                 if live:
-                    batch.advance()
+                    with torch.cuda.stream(bs):
+                        if batch.needs_capture():
+                            with gate:
+                                batch.launch()
+                        else:
+                            batch.launch()
+                    batch.wait()
                     for sid in batch.take_finished():
                         rid = sid_of.pop(sid)
                         r, m, E, H = live.pop(rid)
                         done[rid] = time.perf_counter() - t0
                         used -= r.device_bytes()
                         if keep_states is not None and rid in keep_states:
+                            # on the default stream, the one the set-up thread allocates on
                             states[rid] = (E.clone(), H.clone())
                         m.close()
                         del E, H
@@ -172,12 +203,13 @@ class Server:
                         states[r.rid] = (E.clone(), H.clone())
                     m.close()
                     del E, H
-            if not live and not queue and nxt < len(reqs) and len(done) < len(reqs):
+            if not live and not queue and not pending and nxt < len(reqs) and len(done) < len(reqs):
                 wait = reqs[nxt].arrival - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 0.05))
         if batch is not None:
             batch.close()
+            prep.shutdown()
         makespan = max(done.values()) - min(r.arrival for r in reqs)
         lat = [done[r.rid] - r.arrival for r in reqs]
         work = sum(r.work for r in reqs)

@@ -91,6 +91,45 @@ def test_streaming_kernels_match_plain_bitwise():
         assert np.array_equal(alone[seed][1], mixed[seed][1]), seed
 
 
+def test_launch_wait_matches_advance():
+    """dgm_batch_launch + dgm_batch_wait is dgm_batch_advance in two halves: same results
+    bitwise; a second launch or taking results before the wait is refused; a re-capture
+    is reported only when the set of orders changes."""
+    cases = [(2, 3, 31, 9), (3, 5, 32, 5)]
+    dt = 1e-3
+    runs = []
+    for split in (False, True):
+        b = P.Batch(chunk=4)
+        out, live, caps = {}, {}, []
+        for (n, p, seed, steps) in cases:
+            verts, tets, eps, E, H = _case(n, p, seed)
+            m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
+            Eg, Hg = torch.tensor(E, device="cuda"), torch.tensor(H, device="cuda")
+            live[b.add(m, Eg, Hg, dt, steps)] = (seed, m, Eg, Hg)
+        while b.num_active():
+            if split:
+                caps.append(b.needs_capture())
+                b.launch()
+                with pytest.raises(P.DGMError):
+                    b.launch()
+                with pytest.raises(P.DGMError):
+                    b.take_finished()
+                b.wait()
+            else:
+                b.advance()
+            for sid in b.take_finished():
+                seed, m, Eg, Hg = live.pop(sid)
+                out[seed] = (Eg.cpu().numpy(), Hg.cpu().numpy())
+        b.close()
+        runs.append(out)
+        if split:
+            # chunks of 4: both orders for two launches, then order 3 alone for one
+            assert caps == [True, False, True], caps
+    for seed in runs[0]:
+        assert np.array_equal(runs[0][seed][0], runs[1][seed][0])
+        assert np.array_equal(runs[0][seed][1], runs[1][seed][1])
+
+
 def test_small_trace_both_modes():
     trace = serve.make_trace(num=10, rate=200.0, n_range=(2, 4), p_range=(2, 5), steps_range=(20, 80))
     srv = serve.Server(hbm_budget_bytes=4 * 2 ** 20, chunk=8)  # small budget: admission defers
