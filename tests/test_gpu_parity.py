@@ -276,3 +276,29 @@ def test_rejected_material_leaves_mesh_unchanged():
     m.set_material(np.full(K, 2.0), None)
     changed = host(m.apply_curl(None, H)[0])
     assert not np.array_equal(changed, before[0])
+
+
+def test_operator_spectrum_six_tets_p4():
+    """The library's FP64 operator on the six-tet cube at p = 4, assembled column by
+    column, has the oracle's spectrum (which contains the cube's 2 pi^2 and 3 pi^2
+    resonances with their multiplicities; see the oracle tests)."""
+    verts, tets = synth.kuhn_mesh(1)
+    pr = Pair(verts, tets, 4)
+    Ah, Ae = pr.s.assemble()
+    m = P.Mesh(verts, tets).set_order(4)
+    n = 6 * pr.s.N * 3
+    Ahg, Aeg = np.zeros((n, n)), np.zeros((n, n))
+    for col in range(n):
+        u = np.zeros(n)
+        u[col] = 1.0
+        Ucov = dev(pr.to_cov(u.reshape(6, pr.s.N, 3)), torch.float64)
+        dE, dH = m.apply_curl(Ucov, Ucov)
+        Ahg[:, col] = pr.to_phys(host(dH)).ravel()
+        Aeg[:, col] = pr.to_phys(host(dE)).ravel()
+    lo = np.sort(np.linalg.eigvals(-Ah @ Ae).real)
+    lg = np.sort(np.linalg.eigvals(-Ahg @ Aeg).real)
+    top = lo.max()
+    print(f"max eigenvalue difference {np.abs(lg - lo).max() / top:.2e} of the largest")
+    assert np.abs(lg - lo).max() < 1e-9 * top
+    r = lg / np.pi ** 2
+    assert np.sum(np.abs(r - 2) < 0.01) == 3 and np.sum(np.abs(r - 3) < 0.015) == 2
