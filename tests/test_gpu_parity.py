@@ -304,22 +304,24 @@ def test_operator_spectrum_six_tets_p4():
     assert np.sum(np.abs(r - 2) < 0.01) == 3 and np.sum(np.abs(r - 3) < 0.015) == 2
 
 
-def test_full_size_step_sampled_cube32_p6():
-    """One leapfrog step of the 32^3 x 6, p = 6 FP32 benchmark mesh through dgm_step (the
-    kernels and launch configuration the benchmark times: streaming instantiation, trace
-    exchange between the phases), checked on sampled elements against the oracle stepping
-    their two-ring patch.  The E update of an element reads the H update of its neighbours,
-    which reads E of theirs, so the patch's own outer faces only touch elements two rings
-    out.  Both the new state and its increment over the step are compared."""
-    rng = np.random.default_rng(32)
-    verts, tets = synth.kuhn_mesh(32, 0.1, rng)
-    K, p = tets.shape[0], 6
+@pytest.mark.parametrize("n,p", [(32, 6), (24, 8), (16, 4)])
+def test_full_size_step_sampled(n, p):
+    """One leapfrog step of a full-size FP32 mesh (32^3 x 6 at p = 6 is the benchmark's,
+    streaming instantiation; 24^3 x 6 at p = 8 the dense comparison's; 16^3 x 6 at p = 4 fits
+    the cache, plain instantiation) through dgm_step with half the stable step, checked on
+    sampled elements against the oracle stepping their two-ring patch.  The E update of an
+    element reads the H update of its neighbours, which reads E of theirs, so the patch's own
+    outer faces only touch elements two rings out.  Both the new state and its increment
+    over the step are compared."""
+    rng = np.random.default_rng(n + p)
+    verts, tets = synth.kuhn_mesh(n, 0.1, rng)
+    K = tets.shape[0]
     N = P.num_modes(p)
     eps = rng.choice([1.0, 4.0], size=K)
     m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
     E0 = rng.standard_normal((3, N, K)).astype(np.float32)
     H0 = rng.standard_normal((3, N, K)).astype(np.float32)
-    dt = 4e-4  # the benchmark's step on this mesh (half the stable one)
+    dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=n)
     E, H = dev(E0, torch.float32), dev(H0, torch.float32)
     m.step(E, H, dt, 1)
     E1, H1 = host(E), host(H)
@@ -334,6 +336,6 @@ def test_full_size_step_sampled_cube32_p6():
     E0c, H0c = E0[:, :, centers].astype(np.float64), H0[:, :, centers].astype(np.float64)
     errs = [rel_err(E1[:, :, centers], ref_E), rel_err(H1[:, :, centers], ref_H),
             rel_err(E1[:, :, centers] - E0c, ref_E - E0c), rel_err(H1[:, :, centers] - H0c, ref_H - H0c)]
-    print(f"32^3 p6 one step, {len(centers)} sampled elements ({len(keep)} in the patches): "
+    print(f"{n}^3 p{p} one step (dt {dt:.2e}), {len(centers)} sampled elements ({len(keep)} in the patches): "
           f"E {errs[0]:.2e} H {errs[1]:.2e} dE {errs[2]:.2e} dH {errs[3]:.2e}")
     assert max(errs) < 1e-5
