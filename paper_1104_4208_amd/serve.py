@@ -240,16 +240,23 @@ class Scheduler:
     """Submission interface of the batched server: solves are queued by submit(),
     admitted into batch slots while the HBM budget allows (the oldest first; one
     solve is always admitted when none is running), and advanced together by
-    poll(), chunk steps per call."""
+    poll(), chunk steps per call.  As in Server.run, an admitted solve is set up
+    (mesh, material, field copies) on a worker thread while the batch's chunks run
+    on its own stream, and a launch that re-captures the graph holds the lock every
+    set-up holds."""
 
     def __init__(self, hbm_budget_bytes: int, steps_per_launch: int = 20):
         self.budget = int(hbm_budget_bytes)
         self.batch = D.Batch(int(steps_per_launch))
         self._queue = []
+        self._pending = []  # (tid, t0, dt, nsteps, need, future of the set-up)
         self._live = {}
         self._results = {}
         self._used = 0
         self._next = 0
+        self._stream = None
+        self._prep = cf.ThreadPoolExecutor(max_workers=1)
+        self._gate = threading.Lock()
 
     def submit(self, verts, tets, p, eps, mu, E0, H0, dt, nsteps) -> Ticket:
         """verts/tets: host mesh arrays; eps, mu: per-element arrays or scalars (None
@@ -258,41 +265,69 @@ class Scheduler:
         tid = self._next
         self._next += 1
         self._queue.append((tid, time.perf_counter(), verts, tets, p, eps, mu, E0, H0, dt, nsteps))
+        self._reserve()
         return Ticket(self, tid)
 
-    def poll(self):
-        """Admit what fits, advance every active solve by one chunk, collect results."""
+    def _setup(self, verts, tets, p, eps, mu, E0, H0):
         import torch
 
-        while self._queue:
-            tid, t0, verts, tets, p, eps, mu, E0, H0, dt, nsteps = self._queue[0]
+        with self._gate:
             K = np.asarray(tets).shape[0]
-            need = device_bytes(K, p)
-            if self._live and self._used + need > self.budget:
-                break
-            self._queue.pop(0)
             full = lambda v: None if v is None else np.broadcast_to(np.asarray(v, dtype=np.float64), (K,)).copy()
             m = D.Mesh(verts, tets).set_order(p).set_material(full(eps), full(mu))
             E = torch.as_tensor(E0, dtype=torch.float32, device="cuda").clone().contiguous()
             H = torch.as_tensor(H0, dtype=torch.float32, device="cuda").clone().contiguous()
-            sid = self.batch.add(m, E, H, dt, nsteps)
-            self._live[sid] = (tid, t0, m, E, H, dt, need)
+            torch.cuda.current_stream().synchronize()  # copies done before the batch stream reads them
+            return m, E, H
+
+    def _reserve(self):
+        """Start the set-up of queued solves that fit the budget, oldest first."""
+        while self._queue:
+            tid, t0, verts, tets, p, eps, mu, E0, H0, dt, nsteps = self._queue[0]
+            need = device_bytes(np.asarray(tets).shape[0], p)
+            if (self._live or self._pending) and self._used + need > self.budget:
+                break
+            self._queue.pop(0)
             self._used += need
+            fut = self._prep.submit(self._setup, verts, tets, p, eps, mu, E0, H0)
+            self._pending.append((tid, t0, dt, nsteps, need, fut))
+
+    def poll(self):
+        """Admit what is set up, advance every active solve by one chunk, collect results."""
+        import torch
+
+        if self._stream is None:
+            self._stream = torch.cuda.Stream()
+        self._reserve()
+        while self._pending and (self._pending[0][5].done() or not self._live):
+            tid, t0, dt, nsteps, need, fut = self._pending.pop(0)
+            m, E, H = fut.result()
+            with torch.cuda.stream(self._stream):
+                sid = self.batch.add(m, E, H, dt, nsteps)
+            self._live[sid] = (tid, t0, m, E, H, dt, need)
         if self._live:
-            self.batch.advance()
+            with torch.cuda.stream(self._stream):
+                if self.batch.needs_capture():
+                    with self._gate:
+                        self.batch.launch()
+                else:
+                    self.batch.launch()
+            self.batch.wait()
         for sid in self.batch.take_finished():
             tid, t0, m, E, H, dt, need = self._live.pop(sid)
             energies = m.energy(E, H, dt=dt)
             self._results[tid] = (E, H, energies, time.perf_counter() - t0)
             self._used -= need
             m.close()
+        self._reserve()
 
     def drain(self):
-        while self._queue or self._live:
+        while self._queue or self._pending or self._live:
             self.poll()
 
     def close(self):
         self.batch.close()
+        self._prep.shutdown()
 
 
 def closed_form_error(req, E, H):
