@@ -304,25 +304,28 @@ def test_operator_spectrum_six_tets_p4():
     assert np.sum(np.abs(r - 2) < 0.01) == 3 and np.sum(np.abs(r - 3) < 0.015) == 2
 
 
-@pytest.mark.parametrize("n,p", [(32, 6), (24, 8), (16, 4)])
-def test_full_size_step_sampled(n, p):
+@pytest.mark.parametrize("n,p,dtype,tol", [(32, 6, torch.float32, 1e-5), (24, 8, torch.float32, 1e-5),
+                                            (16, 4, torch.float32, 1e-5), (32, 6, torch.float64, 1e-10),
+                                            (16, 4, torch.float64, 1e-10)])
+def test_full_size_step_sampled(n, p, dtype, tol):
     """One leapfrog step of a full-size FP32 mesh (32^3 x 6 at p = 6 is the benchmark's,
     streaming instantiation; 24^3 x 6 at p = 8 the dense comparison's; 16^3 x 6 at p = 4 fits
     the cache, plain instantiation) through dgm_step with half the stable step, checked on
     sampled elements against the oracle stepping their two-ring patch.  The E update of an
     element reads the H update of its neighbours, which reads E of theirs, so the patch's own
     outer faces only touch elements two rings out.  Both the new state and its increment
-    over the step are compared."""
+    over the step are compared.  In FP64 the 32^3 mesh runs the streaming FP64 kernel."""
     rng = np.random.default_rng(n + p)
     verts, tets = synth.kuhn_mesh(n, 0.1, rng)
     K = tets.shape[0]
     N = P.num_modes(p)
     eps = rng.choice([1.0, 4.0], size=K)
     m = P.Mesh(verts, tets).set_order(p).set_material(eps, None)
-    E0 = rng.standard_normal((3, N, K)).astype(np.float32)
-    H0 = rng.standard_normal((3, N, K)).astype(np.float32)
+    npt = np.float32 if dtype == torch.float32 else np.float64
+    E0 = rng.standard_normal((3, N, K)).astype(npt)
+    H0 = rng.standard_normal((3, N, K)).astype(npt)
     dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=n)
-    E, H = dev(E0, torch.float32), dev(H0, torch.float32)
+    E, H = dev(E0, dtype), dev(H0, dtype)
     m.step(E, H, dt, 1)
     E1, H1 = host(E), host(H)
     centers = np.unique(np.concatenate([rng.integers(0, K, 6), [0, K - 1]]))
@@ -336,6 +339,6 @@ def test_full_size_step_sampled(n, p):
     E0c, H0c = E0[:, :, centers].astype(np.float64), H0[:, :, centers].astype(np.float64)
     errs = [rel_err(E1[:, :, centers], ref_E), rel_err(H1[:, :, centers], ref_H),
             rel_err(E1[:, :, centers] - E0c, ref_E - E0c), rel_err(H1[:, :, centers] - H0c, ref_H - H0c)]
-    print(f"{n}^3 p{p} one step (dt {dt:.2e}), {len(centers)} sampled elements ({len(keep)} in the patches): "
+    print(f"{n}^3 p{p} {dtype} one step (dt {dt:.2e}), {len(centers)} sampled elements ({len(keep)} in the patches): "
           f"E {errs[0]:.2e} H {errs[1]:.2e} dE {errs[2]:.2e} dH {errs[3]:.2e}")
-    assert max(errs) < 1e-5
+    assert max(errs) < tol
