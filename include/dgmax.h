@@ -56,7 +56,7 @@ enum {
   DGM_ERR_OOM = -5,              /* device allocation failed */
   DGM_ERR_HIP = -6,              /* a HIP runtime call failed (message has the HIP error) */
   DGM_ERR_UNSTABLE = -7,         /* non-finite energy detected */
-  DGM_ERR_STATE = -8             /* order not set */
+  DGM_ERR_STATE = -8             /* order not set, or a batch call out of sequence */
 };
 
 /* Thread-local description of the last error returned on this thread. */
@@ -94,7 +94,9 @@ int dgm_set_order(dgm_mesh* mesh, int p);
 /* Per-element piecewise-constant permittivity and permeability (host arrays of
  * length K, each > 0; NULL means 1).  Folds the flat-element mass inverse
  * |det F| eps F^{-1} F^{-T} (Section 3.3.1, eq. massintegral) into per-element
- * factors.  Errors: DGM_ERR_MATERIAL, DGM_ERR_HIP. */
+ * factors.  Every value is checked before anything is uploaded, so a rejected
+ * call leaves the mesh's previous material in place.  Errors: DGM_ERR_MATERIAL,
+ * DGM_ERR_HIP. */
 int dgm_set_material(dgm_mesh* mesh, const double* eps, const double* mu);
 
 /* Semi-discrete right-hand side (Section 2.1, eq. semidiscrete):
@@ -112,7 +114,10 @@ int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void
  * (per element and face two tangents over the (p+1)(p+2)/2 face modes, each
  * padded to a multiple of 4) for the neighbours in the next half step; the
  * handle keeps these two buffers (allocated on first use, K rounded up to a
- * multiple of 64, times 8 x the padded face-mode count, values of dtype each). */
+ * multiple of 64, times 8 x the padded face-mode count, values of dtype each).
+ * When both fields and both trace buffers together exceed 256 MB (the
+ * last-level cache) the kernels give their field accesses the nontemporal hint;
+ * the arithmetic, and so the result, is the same either way. */
 int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
 
 /* dgm_step that also records, after each step n (0-based), signal[n] = sum_i w_i S_i,
