@@ -55,7 +55,7 @@ enum {
   DGM_ERR_MATERIAL = -4,         /* eps or mu not strictly positive / not finite */
   DGM_ERR_OOM = -5,              /* device allocation failed */
   DGM_ERR_HIP = -6,              /* a HIP runtime call failed (message has the HIP error) */
-  DGM_ERR_UNSTABLE = -7,         /* non-finite energy detected */
+  DGM_ERR_UNSTABLE = -7,         /* non-finite energy or state detected */
   DGM_ERR_STATE = -8             /* order not set, or a batch call out of sequence */
 };
 
@@ -106,6 +106,15 @@ int dgm_set_material(dgm_mesh* mesh, const double* eps, const double* mu);
  * input may be NULL too).  Outputs must not alias inputs. */
 int dgm_apply_curl(dgm_mesh* mesh, int dtype, const void* E, const void* H, void* dE, void* dH,
                    hipStream_t stream);
+
+/* Stability check of dgm_step (and dgm_step_probe): with every > 0, after every
+ * `every` steps of a call and after its last step, the FP64 sum of squares of both
+ * fields is formed (one reduction and a stream synchronisation per check); if it is
+ * not finite the call stops there, converts the fields back to the covariant layout
+ * and returns DGM_ERR_UNSTABLE.  A leapfrog run grows without bound when dt exceeds
+ * 2/sqrt(rho) (Section 3), so this catches a time step above the bound.  every = 0
+ * (the default) disables the checks; every < 0 is DGM_ERR_ARG. */
+int dgm_set_check_interval(dgm_mesh* mesh, int64_t every);
 
 /* nsteps symplectic Euler steps in place (Section 3):
  *     H <- H + dt M_mu^{-1} C E,   E <- E - dt M_eps^{-1} C^T H.

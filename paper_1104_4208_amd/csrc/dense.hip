@@ -257,7 +257,7 @@ struct DenseOps {
 
 int dense_build(int p, int prec, DenseOps** out, const char** err) {
   *out = nullptr;
-  if (p < 1 || p > (int)(sizeof(kTables) / sizeof(kTables[0])) - 1) {
+  if (p < 1 || p > (int)(sizeof(kTables) / sizeof(kTables[0])) - 1 || kTables[p].N == 0) {
     *err = "order out of range for the dense variant";
     return -1;
   }

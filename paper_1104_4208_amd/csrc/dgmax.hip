@@ -220,6 +220,7 @@ struct dgm_mesh {
   double* d_partial = nullptr;
   int partial_n = 0;
   double* d_res = nullptr;  // four FP64 reduction results (energies)
+  int64_t check_every = 0;  // dgm_step: steps between finiteness checks (0: none)
   // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
   DenseOps* dense[2] = {nullptr, nullptr};
   float* d_jump = nullptr;
@@ -381,14 +382,21 @@ hipError_t phase(const PhaseArgs<double>& a, int p) { return kPhaseF64[p](a); }
 hipError_t trace(const TraceArgs<float>& a, int p) { return kTraceF32[p](a); }
 hipError_t trace(const TraceArgs<double>& a, int p) { return kTraceF64[p](a); }
 
+// Whether the kernels of order p are built for dtype.  The launcher tables are
+// indexed by order and hold nullptr for orders that were not generated.
+bool order_built(int p, int dtype) {
+  if (p < 1 || p > DGM_MAX_ORDER_F32) return false;
+  if (dtype == DGM_F32) return kPhaseF32[p] != nullptr && kTraceF32[p] != nullptr && kBatchF32[p] != nullptr;
+  return p <= DGM_MAX_ORDER_F64 && kPhaseF64[p] != nullptr && kTraceF64[p] != nullptr;
+}
+
 int check_order(dgm_mesh* m, int dtype) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
   if (dtype != DGM_F32 && dtype != DGM_F64) return fail(DGM_ERR_ARG, "dtype must be DGM_F32 or DGM_F64");
   if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
-  const int pmax = dtype == DGM_F32 ? DGM_MAX_ORDER_F32 : DGM_MAX_ORDER_F64;
-  if (m->p > pmax)
+  if (!order_built(m->p, dtype))
     return fail(DGM_ERR_ARG, "order " + std::to_string(m->p) + " not compiled for this dtype (max " +
-                                 std::to_string(pmax) + ")");
+                                 std::to_string(dtype == DGM_F32 ? DGM_MAX_ORDER_F32 : DGM_MAX_ORDER_F64) + ")");
   return DGM_OK;
 }
 
@@ -477,7 +485,28 @@ int ensure_partial(dgm_mesh* m, int nb) {
   return DGM_OK;
 }
 
+// FP64 sum of squares of both fields (any frame), synchronised: finite iff every
+// coefficient is finite (short of overflow in the squares).
+template <typename R>
+int finite_state(dgm_mesh* m, const R* E, const R* H, size_t n, int nb, bool* ok, hipStream_t s) {
+  if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
+  for (int f = 0; f < 2; ++f) {
+    const R* X = f == 0 ? E : H;
+    hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, X, X, n, m->d_partial);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, m->d_res + f);
+    HIP_TRY(hipGetLastError());
+  }
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, m->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *ok = std::isfinite(h[0]) && std::isfinite(h[1]);
+  return DGM_OK;
+}
+
 // With w and d_sig: after step n, d_sig[n] = sum_i w_i E_i (E in the stored frame).
+// With m->check_every > 0 the state is checked after every check_every steps (and after
+// the last); a non-finite state ends the run (fields converted back) with DGM_ERR_UNSTABLE.
 template <typename R>
 int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s, const R* w = nullptr,
               double* d_sig = nullptr) {
@@ -485,7 +514,8 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
   if (nsteps == 0) return DGM_OK;
   const size_t n = (size_t)3 * num_modes(m->p) * m->K;
   const int nb = (int)std::min<size_t>(kDotBlocks, (n + kRedThreads - 1) / kRedThreads);
-  if (w && (rc = ensure_partial(m, nb))) return rc;
+  const int64_t every = m->check_every;
+  if ((w || every > 0) && (rc = ensure_partial(m, nb))) return rc;
   R *TE, *TH;
   if ((rc = ensure_traces<R>(m, &TE, &TH))) return rc;
   if ((rc = convert<R>(m, E, 0, true, s))) return rc;
@@ -501,6 +531,16 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_sig + it);
       HIP_TRY(hipGetLastError());
+    }
+    if (every > 0 && ((it + 1) % every == 0 || it + 1 == nsteps)) {
+      bool ok = true;
+      if ((rc = finite_state<R>(m, E, H, n, nb, &ok, s))) return rc;
+      if (!ok) {
+        if ((rc = convert<R>(m, E, 0, false, s))) return rc;
+        if ((rc = convert<R>(m, H, 1, false, s))) return rc;
+        return fail(DGM_ERR_UNSTABLE, "non-finite state after step " + std::to_string(it + 1) +
+                                          " (time step above the stability bound?)");
+      }
     }
   }
   if ((rc = convert<R>(m, E, 0, false, s))) return rc;
@@ -810,7 +850,7 @@ int dgm_num_elements(const dgm_mesh* m, int64_t* K) {
 
 int dgm_set_order(dgm_mesh* m, int p) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
-  if (p < 1 || p > DGM_MAX_ORDER_F32) return fail(DGM_ERR_ARG, "order out of range");
+  if (!order_built(p, DGM_F32)) return fail(DGM_ERR_ARG, "order " + std::to_string(p) + " not built");
   if (m->p != p) {
     for (int q = 0; q < 2; ++q) {
       dense_free(m->dense[q]);
@@ -818,6 +858,12 @@ int dgm_set_order(dgm_mesh* m, int p) {
     }
   }
   m->p = p;
+  return DGM_OK;
+}
+
+int dgm_set_check_interval(dgm_mesh* m, int64_t every) {
+  if (!m || every < 0) return fail(DGM_ERR_ARG, "bad check interval");
+  m->check_every = every;
   return DGM_OK;
 }
 
@@ -972,6 +1018,9 @@ int batch_capture(dgm_batch* b) {
   if (b->graph) HIP_TRY(hipGraphDestroy(b->graph));
   b->exec = nullptr;
   b->graph = nullptr;
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p)
+    if ((b->live_orders & (1u << p)) && !kBatchF32[p])
+      return fail(DGM_ERR_ARG, "batched kernel of order " + std::to_string(p) + " not built");
   if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;

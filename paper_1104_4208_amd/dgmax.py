@@ -43,6 +43,7 @@ SIGNATURES = {
     "dgm_num_elements": (_c_i, [_c_p, _pi64]),
     "dgm_set_order": (_c_i, [_c_p, _c_i]),
     "dgm_set_material": (_c_i, [_c_p, _pd, _pd]),
+    "dgm_set_check_interval": (_c_i, [_c_p, _c_i64]),
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
     "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
@@ -189,6 +190,12 @@ class Mesh:
         _check(load_library().dgm_set_material(self._h, ep, mp))
         return self
 
+    def set_check_interval(self, every: int):
+        """dgm_step checks the state every `every` steps (0: never) and raises
+        DGMError (DGM_ERR_UNSTABLE) on a non-finite one."""
+        _check(load_library().dgm_set_check_interval(self._h, int(every)))
+        return self
+
     def _field(self, t, name):
         torch = _torch()
         if t is None:
@@ -199,16 +206,30 @@ class Mesh:
             raise DGMError(f"{name} must be contiguous with shape (3, {self.N}, {self.K})")
         return t
 
+    def _fields(self, **named):
+        """Check every given field (None skipped) with _field and that they share one
+        dtype; returns the checked tensors in order and the common dtype code."""
+        out = [self._field(t, n) for n, t in named.items()]
+        given = [(n, t) for n, t in zip(named, out) if t is not None]
+        if not given:
+            raise DGMError("no field given")
+        dt = given[0][1].dtype
+        for n, t in given:
+            if t.dtype != dt:
+                raise DGMError(f"{n} has dtype {t.dtype}, expected {dt} (all fields must share one dtype)")
+        return out, _dtype_code(given[0][1])
+
     def zeros(self, dtype=None):
         torch = _torch()
         return torch.zeros((3, self.N, self.K), dtype=dtype or torch.float32, device="cuda")
 
     def apply_curl(self, E=None, H=None, dE=None, dH=None):
         """Returns (dE, dH) = (-M_eps^{-1} C^T H, M_mu^{-1} C E)."""
-        E, H = self._field(E, "E"), self._field(H, "H")
-        ref = E if E is not None else H
-        code = _dtype_code(ref)
         torch = _torch()
+        if E is None and H is None:
+            raise DGMError("apply_curl needs E or H")
+        (E, H, dE, dH), code = self._fields(E=E, H=H, dE=dE if H is not None else None,
+                                            dH=dH if E is not None else None)
         if H is not None and dE is None:
             dE = torch.empty_like(H)
         if E is not None and dH is None:
@@ -240,17 +261,22 @@ class Mesh:
 
     def energy(self, E, H, H_next=None, dt: float = 0.0):
         """(W, Q) in FP64; Q uses H_next (computed as H + dt dH(E) when None)."""
-        E, H, Hn = self._field(E, "E"), self._field(H, "H"), self._field(H_next, "H_next")
+        if E is None or H is None:
+            raise DGMError("energy needs E and H")
+        (E, H, Hn), code = self._fields(E=E, H=H, H_next=H_next)
         out = (ctypes.c_double * 2)()
-        _check(load_library().dgm_energy(self._h, _dtype_code(E), _ptr(E), _ptr(H), _ptr(Hn), float(dt), out,
+        _check(load_library().dgm_energy(self._h, code, _ptr(E), _ptr(H), _ptr(Hn), float(dt), out,
                                          _stream()))
         return out[0], out[1]
 
     def apply_curl_dense(self, E=None, H=None, prec: int = DGM_BF16, dE=None, dH=None):
         """Dense matrix-core variant of apply_curl (FP32 fields, 16-bit operands)."""
-        E, H = self._field(E, "E"), self._field(H, "H")
         torch = _torch()
-        for t in (E, H):
+        if E is None and H is None:
+            raise DGMError("apply_curl_dense needs E or H")
+        (E, H, dE, dH), _ = self._fields(E=E, H=H, dE=dE if H is not None else None,
+                                         dH=dH if E is not None else None)
+        for t in (E, H, dE, dH):
             if t is not None and t.dtype != torch.float32:
                 raise DGMError("the dense variant takes float32 fields")
         if H is not None and dE is None:

@@ -786,7 +786,7 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     A, Ai = fr["A"], fr["Ainv"]
     lines = ["// Generated by gen/emit.py: derivative frame and compiled orders.",
              f"#define DGM_MAX_ORDER_F32 {max(orders)}",
-             f"#define DGM_MAX_ORDER_F64 {min(max(orders), F64_MAX_ORDER)}",
+             f"#define DGM_MAX_ORDER_F64 {max([p for p in orders if p <= F64_MAX_ORDER], default=0)}",
              "static const double kFrameA[9] = {" + ", ".join(float(v).hex() for v in A.ravel()) + "};",
              "static const double kFrameAinv[9] = {" + ", ".join(float(v).hex() for v in Ai.ravel()) + "};",
              f"static const double kFrameDetA = {float(fr['detA']).hex()};"]
@@ -800,16 +800,33 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
         if p <= F64_MAX_ORDER:
             decl.append(f"hipError_t dgm_launch_trace_p{p}_f64(const TraceArgs<double>& a);")
     lines += decl
-    lines.append("static hipError_t (*const kTraceF32[])(const TraceArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_trace_p{p}_f32" for p in orders) + "};")
-    lines.append("static hipError_t (*const kTraceF64[])(const TraceArgs<double>&) = {nullptr, " + ", ".join(f"dgm_launch_trace_p{p}_f64" for p in orders if p <= F64_MAX_ORDER) + "};")
-    lines.append("static hipError_t (*const kPhaseF32[])(const PhaseArgs<float>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f32" for p in orders) + "};")
     for p in orders:
         lines.append(f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a);")
-    lines.append("static hipError_t (*const kBatchF32[])(const BatchArgs&) = {nullptr, " + ", ".join(f"dgm_launch_batch_p{p}_f32" for p in orders) + "};")
-    lines.append("static hipError_t (*const kPhaseF64[])(const PhaseArgs<double>&) = {nullptr, " + ", ".join(f"dgm_launch_phase_p{p}_f64" for p in orders if p <= F64_MAX_ORDER) + "};")
+    lines += launcher_tables(orders)
     _write_if_changed(os.path.join(outdir, "frame.inc"), "\n".join(lines) + "\n")
     _write_if_changed(os.path.join(outdir, "tables.inc"), emit_host_tables(orders))
     return units
+
+
+def launcher_tables(orders):
+    """Launcher tables indexed by order: entry p is the launcher of order p, nullptr
+    where order p was not built (or is not instantiated for that precision).  Every
+    table has DGM_MAX_ORDER_F32 + 1 entries, so the host may index it by any order
+    up to that bound and must check the entry before calling it."""
+    top = max(orders)
+
+    def table(decl, name, present):
+        ents = ", ".join(name.format(p=p) if (p in orders and present(p)) else "nullptr" for p in range(top + 1))
+        return f"static {decl.format(n=top + 1)} = {{{ents}}};"
+
+    f64 = lambda p: p <= F64_MAX_ORDER
+    return [
+        table("hipError_t (*const kTraceF32[{n}])(const TraceArgs<float>&)", "dgm_launch_trace_p{p}_f32", lambda p: True),
+        table("hipError_t (*const kTraceF64[{n}])(const TraceArgs<double>&)", "dgm_launch_trace_p{p}_f64", f64),
+        table("hipError_t (*const kPhaseF32[{n}])(const PhaseArgs<float>&)", "dgm_launch_phase_p{p}_f32", lambda p: True),
+        table("hipError_t (*const kPhaseF64[{n}])(const PhaseArgs<double>&)", "dgm_launch_phase_p{p}_f64", f64),
+        table("hipError_t (*const kBatchF32[{n}])(const BatchArgs&)", "dgm_launch_batch_p{p}_f32", lambda p: True),
+    ]
 
 
 def emit_host_tables(orders):
@@ -830,9 +847,13 @@ def emit_host_tables(orders):
         for f in range(4):
             r, c = np.nonzero(t.T[f])
             L.append(f"static const SparseEntry kT{f}_p{p}[] = {{" + ", ".join(f"{{{i},{j},{float(t.T[f][i, j]).hex()}}}" for i, j in zip(r, c)) + "};")
-    L.append("static const OrderTables kTables[] = {")
-    L.append("  {0, 0, {nullptr, nullptr, nullptr}, {0, 0, 0}, {nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, {}, {}},")
-    for p in orders:
+    empty = "  {0, 0, {nullptr, nullptr, nullptr}, {0, 0, 0}, {nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}, {}, {}},"
+    L.append("// indexed by order; N = 0 marks an order that was not built")
+    L.append(f"static const OrderTables kTables[{max(orders) + 1}] = {{")
+    for p in range(max(orders) + 1):
+        if p not in orders:
+            L.append(empty)
+            continue
         t = TB.build(p)
         g, Lp = TB.face_weights(t)
         nD = [int(np.count_nonzero(t.D[d])) for d in range(3)]

@@ -75,3 +75,55 @@ def test_mesh_errors_are_reported_before_device_work():
     assert lib.dgm_create_mesh(None, 0, None, 0, None) == -1
     assert lib.dgm_set_order(None, 2) == -1
     assert lib.dgm_step(None, 0, None, None, 0.1, 1, None) == -1
+
+
+def _hostmesh(monkeypatch, K=6, p=2):
+    """A Mesh object without a device handle whose field check accepts host tensors, so
+    the binding's argument checks can run here; any library call fails the test."""
+    import torch
+
+    m = object.__new__(P.Mesh)
+    m._h, m.K, m.p = None, K, p
+    N = (p + 1) * (p + 2) * (p + 3) // 6
+    monkeypatch.setattr(P.Mesh, "N", property(lambda self: N))
+
+    def field(self, t, name):
+        if t is None:
+            return None
+        if tuple(t.shape) != (3, N, K) or not t.is_contiguous():
+            raise D.DGMError(f"{name} shape")
+        return t
+
+    monkeypatch.setattr(P.Mesh, "_field", field)
+
+    def no_lib(*a, **k):
+        raise AssertionError("reached the library")
+
+    monkeypatch.setattr(D, "load_library", no_lib)
+    z = lambda dt: torch.zeros((3, N, K), dtype=dt)
+    return m, z
+
+
+def test_binding_rejects_mixed_dtypes_before_the_library(monkeypatch):
+    import torch
+
+    m, z = _hostmesh(monkeypatch)
+    f32, f64 = torch.float32, torch.float64
+    with pytest.raises(D.DGMError, match="H has dtype"):
+        m.apply_curl(z(f64), z(f32))
+    with pytest.raises(D.DGMError, match="dE has dtype"):
+        m.apply_curl(None, z(f64), dE=z(f32))
+    with pytest.raises(D.DGMError, match="dH has dtype"):
+        m.apply_curl(z(f32), None, dH=z(f64))
+    with pytest.raises(D.DGMError, match="H_next has dtype"):
+        m.energy(z(f64), z(f64), H_next=z(f32))
+    with pytest.raises(D.DGMError, match="H has dtype"):
+        m.energy(z(f64), z(f32))
+    with pytest.raises(D.DGMError, match="dH has dtype"):
+        m.apply_curl_dense(z(f32), None, dH=z(f64))
+    with pytest.raises(D.DGMError, match="float32"):
+        m.apply_curl_dense(None, z(f64), dE=z(f64))
+    with pytest.raises(D.DGMError, match="shape"):
+        m.apply_curl(None, z(f32), dE=torch.zeros((3, 10, 5)))
+    with pytest.raises(D.DGMError, match="needs"):
+        m.energy(None, z(f32))

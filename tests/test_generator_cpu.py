@@ -62,3 +62,26 @@ def test_tile_offsets_are_a_bijection():
     offs = np.array([((f * FQ + j) * emit.LANES + l) * 4 + i
                      for f in range(4) for j in range(FQ) for l in range(emit.LANES) for i in range(4)])
     assert np.array_equal(np.sort(offs), np.arange(emit.LANES * ES))
+
+
+def test_launcher_tables_are_indexed_by_order(tmp_path):
+    """A build of a subset of the orders (here 2 and 4) puts the launcher of order p at
+    index p of every table and nullptr at the orders it did not build, so the host can
+    index by order and reject an order whose entry is empty."""
+    import re
+
+    emit.emit_all(str(tmp_path), [2, 4])
+    src = (tmp_path / "frame.inc").read_text()
+    assert "#define DGM_MAX_ORDER_F32 4" in src
+    for name, stem in (("kTraceF32", "trace_p{}_f32"), ("kTraceF64", "trace_p{}_f64"), ("kPhaseF32", "phase_p{}_f32"),
+                       ("kPhaseF64", "phase_p{}_f64"), ("kBatchF32", "batch_p{}_f32")):
+        m = re.search(name + r"\[(\d+)\]\)\([^)]*\) = \{([^}]*)\};", src)
+        assert m, name
+        ents = [e.strip() for e in m.group(2).split(",")]
+        assert int(m.group(1)) == 5 and len(ents) == 5, name
+        for p, e in enumerate(ents):
+            assert e == (f"dgm_launch_{stem.format(p)}" if p in (2, 4) else "nullptr"), (name, p, e)
+    host = (tmp_path / "tables.inc").read_text()
+    rows = host[host.index("kTables[5] = {"):].splitlines()[1:6]
+    assert [r.strip().startswith("{0, 0,") for r in rows] == [True, True, False, True, False]
+    assert rows[2].strip().startswith("{10, 6,") and rows[4].strip().startswith("{35, 15,")

@@ -342,3 +342,27 @@ def test_full_size_step_sampled(n, p, dtype, tol):
     print(f"{n}^3 p{p} {dtype} one step (dt {dt:.2e}), {len(centers)} sampled elements ({len(keep)} in the patches): "
           f"E {errs[0]:.2e} H {errs[1]:.2e} dE {errs[2]:.2e} dH {errs[3]:.2e}")
     assert max(errs) < tol
+
+
+def test_check_interval_reports_unstable():
+    """With a check interval, dgm_step stops a run whose state is no longer finite
+    (time step far above 2/sqrt(rho): leapfrog grows by about (dt w)^2 per step, so FP32
+    overflows within a few tens of steps) and returns DGM_ERR_UNSTABLE; a stable step
+    passes every check, and without checks the same unstable call returns DGM_OK."""
+    verts, tets = synth.kuhn_mesh(2)
+    m = P.Mesh(verts, tets).set_order(2)
+    K, N = tets.shape[0], P.num_modes(2)
+    rng = np.random.default_rng(17)
+    E0 = dev(rng.standard_normal((3, N, K)), torch.float32)
+    dt, _ = m.estimate_dt(cfl=0.5, iters=20, seed=1)
+    E, H = E0.clone(), torch.zeros_like(E0)
+    m.set_check_interval(10)
+    m.step(E, H, dt, 100)  # stable: every check passes
+    assert torch.isfinite(E).all() and torch.isfinite(H).all()
+    E, H = E0.clone(), torch.zeros_like(E0)
+    with pytest.raises(P.DGMError, match="DGM_ERR_UNSTABLE"):
+        m.step(E, H, 100 * dt, 200)
+    m.set_check_interval(0)
+    E, H = E0.clone(), torch.zeros_like(E0)
+    m.step(E, H, 100 * dt, 200)
+    assert not bool(torch.isfinite(E).all())
