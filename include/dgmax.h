@@ -139,6 +139,21 @@ int dgm_step(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nst
 int dgm_step_probe(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, const void* w,
                    double* signal, hipStream_t stream);
 
+/* dgm_step for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same arithmetic (bitwise equal results), but the trace buffers and the reduction
+ * buffers of the stability check live in a static device workspace of
+ * DGM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends; no hipMalloc, hipFree or allocating library routine is called.  A mesh
+ * needs 2 x ceil(K/64) x 64 x 8 x ceil((p+1)(p+2)/8) x 4 values of dtype plus 4 KiB
+ * (about 64 MiB holds 37,000 tetrahedra at p = 6 in FP32); larger meshes are rejected
+ * with DGM_ERR_ARG before any work.  Every call on one GPU shares that GPU's workspace:
+ * calls that overlap in time on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  The workspace needs no clearing (every value is written
+ * before it is read).  Other arguments, errors and the check interval as dgm_step. */
+#define DGM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dgm_step_noalloc(dgm_mesh* mesh, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t stream);
+
 /* FP64 energies: out[0] = W = 1/2 (E, M_eps E) + 1/2 (H, M_mu H)  (Section 2.1),
  * out[1] = Q = 1/2 (E, M_eps E) + 1/2 (H, M_mu H_next), the quantity the
  * H-first symplectic Euler step conserves exactly.  H_next is the H of the next

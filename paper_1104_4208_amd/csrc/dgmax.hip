@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -487,37 +488,62 @@ int ensure_partial(dgm_mesh* m, int nb) {
 
 // FP64 sum of squares of both fields (any frame), synchronised: finite iff every
 // coefficient is finite (short of overflow in the squares).
+// Device workspace of a run of leapfrog steps: the two trace buffers, kDotBlocks FP64
+// partial sums and two FP64 results (the last two only for checks and probes).
 template <typename R>
-int finite_state(dgm_mesh* m, const R* E, const R* H, size_t n, int nb, bool* ok, hipStream_t s) {
-  if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
+struct StepWork {
+  R* TE = nullptr;
+  R* TH = nullptr;
+  double* partial = nullptr;
+  double* res = nullptr;
+};
+
+// FP64 sum of squares of both fields (any frame), synchronised: finite iff every
+// coefficient is finite (short of overflow in the squares).
+template <typename R>
+int finite_state(const StepWork<R>& ws, const R* E, const R* H, size_t n, int nb, bool* ok, hipStream_t s) {
   for (int f = 0; f < 2; ++f) {
     const R* X = f == 0 ? E : H;
-    hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, X, X, n, m->d_partial);
+    hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, X, X, n, ws.partial);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, m->d_res + f);
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, ws.partial, nb, ws.res + f);
     HIP_TRY(hipGetLastError());
   }
   double h[2];
-  HIP_TRY(hipMemcpyAsync(h, m->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h, ws.res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   *ok = std::isfinite(h[0]) && std::isfinite(h[1]);
+  return DGM_OK;
+}
+
+// Workspace of dgm_step / dgm_step_probe, owned by the mesh handle (grown on demand).
+template <typename R>
+int mesh_work(dgm_mesh* m, bool reductions, StepWork<R>* ws) {
+  int rc;
+  if ((rc = ensure_traces<R>(m, &ws->TE, &ws->TH))) return rc;
+  if (reductions) {
+    if ((rc = ensure_partial(m, kDotBlocks))) return rc;
+    if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
+    ws->partial = m->d_partial;
+    ws->res = m->d_res;
+  }
   return DGM_OK;
 }
 
 // With w and d_sig: after step n, d_sig[n] = sum_i w_i E_i (E in the stored frame).
 // With m->check_every > 0 the state is checked after every check_every steps (and after
 // the last); a non-finite state ends the run (fields converted back) with DGM_ERR_UNSTABLE.
+// ws: trace buffers (always) and, for checks or probes, the reduction buffers.
 template <typename R>
-int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s, const R* w = nullptr,
-              double* d_sig = nullptr) {
+int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s, const StepWork<R>& ws,
+              const R* w = nullptr, double* d_sig = nullptr) {
   int rc;
   if (nsteps == 0) return DGM_OK;
   const size_t n = (size_t)3 * num_modes(m->p) * m->K;
   const int nb = (int)std::min<size_t>(kDotBlocks, (n + kRedThreads - 1) / kRedThreads);
   const int64_t every = m->check_every;
-  if ((w || every > 0) && (rc = ensure_partial(m, nb))) return rc;
-  R *TE, *TH;
-  if ((rc = ensure_traces<R>(m, &TE, &TH))) return rc;
+  R* const TE = ws.TE;
+  R* const TH = ws.TH;
   if ((rc = convert<R>(m, E, 0, true, s))) return rc;
   if ((rc = convert<R>(m, H, 1, true, s))) return rc;
   if ((rc = run_trace<R>(m, E, 0, TE, s))) return rc;
@@ -527,14 +553,14 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
     if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s))) return rc;
     if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s))) return rc;
     if (w) {
-      hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, (const R*)E, w, n, m->d_partial);
+      hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, (const R*)E, w, n, ws.partial);
       HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_sig + it);
+      hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, ws.partial, nb, d_sig + it);
       HIP_TRY(hipGetLastError());
     }
     if (every > 0 && ((it + 1) % every == 0 || it + 1 == nsteps)) {
       bool ok = true;
-      if ((rc = finite_state<R>(m, E, H, n, nb, &ok, s))) return rc;
+      if ((rc = finite_state<R>(ws, E, H, n, nb, &ok, s))) return rc;
       if (!ok) {
         if ((rc = convert<R>(m, E, 0, false, s))) return rc;
         if ((rc = convert<R>(m, H, 1, false, s))) return rc;
@@ -891,8 +917,16 @@ int dgm_step(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps
   int rc = check_order(m, dtype);
   if (rc) return rc;
   if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
-  return dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s)
-                          : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s);
+  if (nsteps == 0) return DGM_OK;
+  const bool red = m->check_every > 0;
+  if (dtype == DGM_F32) {
+    StepWork<float> ws;
+    if ((rc = mesh_work<float>(m, red, &ws))) return rc;
+    return step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, ws);
+  }
+  StepWork<double> ws;
+  if ((rc = mesh_work<double>(m, red, &ws))) return rc;
+  return step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, ws);
 }
 
 int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps, const void* w,
@@ -904,8 +938,15 @@ int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t 
   if (nsteps == 0) return DGM_OK;
   double* d_sig = nullptr;
   HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&d_sig), (size_t)nsteps * sizeof(double), s));
-  rc = dtype == DGM_F32 ? step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, (const float*)w, d_sig)
-                        : step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, (const double*)w, d_sig);
+  if (dtype == DGM_F32) {
+    StepWork<float> ws;
+    rc = mesh_work<float>(m, true, &ws);
+    if (!rc) rc = step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, ws, (const float*)w, d_sig);
+  } else {
+    StepWork<double> ws;
+    rc = mesh_work<double>(m, true, &ws);
+    if (!rc) rc = step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, ws, (const double*)w, d_sig);
+  }
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(signal, d_sig, (size_t)nsteps * sizeof(double), hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipFreeAsync(d_sig, s);  // freed on every path
@@ -915,6 +956,87 @@ int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t 
   HIP_TRY(e2);
   HIP_TRY(e3);
   return DGM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free step
+// Workspace of dgm_step_noalloc: a file-scope device array, one copy per GPU the library
+// runs on, held until the process ends.  In host code `scratch` names a host-side stand-in,
+// not the device memory: its device address is resolved once per device with
+// hipGetSymbolAddress (with that device current) and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[DGM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first call there).
+int scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(DGM_ERR_ARG, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(DGM_ERR_HIP, "hipGetSymbolAddress returned a null workspace address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DGM_OK;
+}
+
+constexpr size_t kScratchPartialOff = 0;                                         // kDotBlocks doubles
+constexpr size_t kScratchResOff = kScratchPartialOff + kDotBlocks * sizeof(double);  // 2 doubles
+constexpr size_t kScratchTraceOff = (kScratchResOff + 2 * sizeof(double) + 255) & ~size_t(255);
+
+// Bytes of the workspace a run on mesh m in precision rsize needs.
+size_t noalloc_bytes(const dgm_mesh* m, size_t rsize) {
+  const size_t per = (trace_words(m->K, m->p) * rsize + 255) & ~size_t(255);
+  return kScratchTraceOff + 2 * per;
+}
+
+// The workspace laid out as trace buffers and reduction buffers (nothing is allocated;
+// nothing needs clearing: the trace buffers are written before they are read and the
+// reductions write their results before reading them).
+template <typename R>
+void noalloc_work(const dgm_mesh* m, void* base, StepWork<R>* ws) {
+  unsigned char* b = static_cast<unsigned char*>(base);
+  const size_t per = (trace_words(m->K, m->p) * sizeof(R) + 255) & ~size_t(255);
+  ws->partial = reinterpret_cast<double*>(b + kScratchPartialOff);
+  ws->res = reinterpret_cast<double*>(b + kScratchResOff);
+  ws->TE = reinterpret_cast<R*>(b + kScratchTraceOff);
+  ws->TH = reinterpret_cast<R*>(b + kScratchTraceOff + per);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgm_step_noalloc(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
+  const size_t rsize = dtype == DGM_F32 ? sizeof(float) : sizeof(double);
+  const size_t need = noalloc_bytes(m, rsize);
+  if (need > (size_t)DGM_NOALLOC_SCRATCH_BYTES)
+    return fail(DGM_ERR_ARG, "mesh too large for the allocation-free step: needs " + std::to_string(need) +
+                                 " bytes of workspace, the library holds " +
+                                 std::to_string((size_t)DGM_NOALLOC_SCRATCH_BYTES));
+  if (nsteps == 0) return DGM_OK;
+  void* base = nullptr;
+  if ((rc = scratch_address(&base))) return rc;
+  if (dtype == DGM_F32) {
+    StepWork<float> ws;
+    noalloc_work<float>(m, base, &ws);
+    return step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, ws);
+  }
+  StepWork<double> ws;
+  noalloc_work<double>(m, base, &ws);
+  return step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, ws);
 }
 
 int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void* Hn, double dt, double out[2],

@@ -46,6 +46,7 @@ SIGNATURES = {
     "dgm_set_check_interval": (_c_i, [_c_p, _c_i64]),
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
+    "dgm_step_noalloc": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
     "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
     "dgm_step_probe": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p, _pd, _c_p]),
     "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
@@ -244,6 +245,16 @@ class Mesh:
         if E.dtype != H.dtype:
             raise DGMError("E and H must share a dtype")
         _check(load_library().dgm_step(self._h, _dtype_code(E), _ptr(E), _ptr(H), float(dt), int(nsteps), _stream()))
+        return E, H
+
+    def step_noalloc(self, E, H, dt: float, nsteps: int = 1):
+        """dgm_step_noalloc: dgm_step with the library's static device workspace (no
+        device allocation; meshes above the workspace size raise)."""
+        E, H = self._field(E, "E"), self._field(H, "H")
+        if E.dtype != H.dtype:
+            raise DGMError("E and H must share a dtype")
+        _check(load_library().dgm_step_noalloc(self._h, _dtype_code(E), _ptr(E), _ptr(H), float(dt), int(nsteps),
+                                               _stream()))
         return E, H
 
     def step_probe(self, E, H, dt: float, nsteps: int, w):
