@@ -17,6 +17,8 @@ H first).  Stored per workload (``run_<name>.npz``, plain arrays, no pickles):
                         elements at each of the C checkpoints (oracle mode order)
   W, Q                  (C,) FP64 energy and leapfrog invariant of the whole mesh
   E0W                   energy of the initial state
+  E_end, H_end          (K, N, 3) the whole final state, for the energy-norm error
+                        of the run
 
 Workload recipes (same seeds and draw order as the full-size workloads):
   cfg2  p = 4, eps = mu = 1, three cavity modes with N(0,1) amplitudes (seed 2),
@@ -103,7 +105,7 @@ def make(name):
     out = os.path.join(HERE, f"run_{name}.npz")
     np.savez_compressed(out, verts=verts, tets=tets, eps=eps, mu=mu, dt=dt, steps=r["steps"], every=r["every"],
                         p=r["p"], seed=r["seed"], init_checksum=checksum, sample=smp, E_s=E_s, H_s=H_s, W=W, Q=Q,
-                        E0W=W0)
+                        E0W=W0, E_end=E, H_end=H)
     print(f"{name}: wrote {out}", flush=True)
 
 
