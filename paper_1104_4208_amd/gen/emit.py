@@ -55,6 +55,7 @@ LDS_BUDGET = 160 * 1024  # bytes of LDS per compute unit
 F64_MAX_ORDER = 6        # highest order also instantiated in FP64 (its staged field must fit in LDS)
 TRACE_ROWS = 32          # face modes per trace job (bounds the job's accumulators)
 LDS_GROUP = 8            # mode blocks per basic block in a stream
+GROUP_LOADS = 32         # LDS loads per basic block in a stream (blocks of the factored traces are large)
 
 
 class _Stream:
@@ -77,8 +78,14 @@ class _Stream:
         if not blocks:
             return
         a_(ind + "size_t o = 0;")
-        for g0 in range(0, len(blocks), LDS_GROUP):
-            grp = blocks[g0:g0 + LDS_GROUP]
+        groups, cur = [], []
+        for b in blocks:
+            if cur and (len(cur) == LDS_GROUP or sum(len(x[0]) for x in cur) + len(b[0]) > GROUP_LOADS):
+                groups.append(cur)
+                cur = []
+            cur.append(b)
+        groups.append(cur)
+        for grp in groups:
             a_(ind + "asm volatile(\"\" : \"+s\"(o));")
             a_(ind + "if (o == 0) {")
             names = []
@@ -98,6 +105,131 @@ OUT_ROWS = 32     # volume modes per output job (3 components each)
 CYC = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
 
 
+
+FACTORED = (0, 3)  # faces whose trace goes through the collapsed tensor-product factors
+
+
+def _blocks(t):
+    """Volume modes grouped by (m, k) = (i + j, k): the rows (i, m - i, k), i = 0..m,
+    which the first trace factor A couples (one block per column block of A)."""
+    idx = {md: r for r, md in enumerate(t.modes)}
+    return [[idx[(i, m - i, k)] for i in range(m + 1)] for m in range(t.p + 1) for k in range(t.p - m + 1)]
+
+
+def _fac_A(t, f):
+    return t.fac["A3"] if f == 3 else t.fac["A0"]
+
+
+def _tangent_terms(g, f, k):
+    """Nonzero (component, weight) pairs of the tangential scalar g_fk . w."""
+    return [(c, float(g[f][k][c])) for c in range(3) if g[f][k][c] != 0.0]
+
+
+def _in_cost(g, f, k, nin):
+    """LDS loads plus the tangential combination per streamed volume mode."""
+    n = len(_tangent_terms(g, f, k))
+    return nin * (2 * n - 1)
+
+
+def _fac_trace_parts(t, f, rows):
+    """Dependencies of a factored trace job producing face rows `rows` (psi basis) of
+    face f: (rows accumulated before the face-basis change -- on face 0 the
+    collapsed-basis rows C couples to `rows` -- and per (m, k) block the needed
+    intermediates with their volume inputs)."""
+    Bm, C, X = t.fac["B"], t.fac["C"], t.fac["X"]
+    A = _fac_A(t, f)
+    brows = sorted({int(c) for r in rows for c in np.nonzero(C[r])[0]}) if f == 0 else list(rows)
+    xs = sorted({int(x) for c in brows for x in np.nonzero(Bm[c])[0]})
+    byblk = {}
+    for x in xs:
+        a, m, k = X[x]
+        byblk.setdefault((m, k), []).append(x)
+    parts = []
+    for key in sorted(byblk):
+        xl = byblk[key]
+        ins = sorted({int(c) for x in xl for c in np.nonzero(A[x])[0]})
+        parts.append((xl, ins))
+    return brows, parts
+
+
+def _trace_costs(t, g, f, k, rows):
+    """(direct, factored) instruction estimates of the trace job (face f, tangent k,
+    face rows): streamed inputs, one FMA per operator entry, the 16-byte stores."""
+    st = len({m // 4 for m in rows})
+    T = t.T[f][rows]
+    d = _in_cost(g, f, k, int(np.count_nonzero(np.any(T != 0, axis=0)))) + int(np.count_nonzero(T)) + st
+    if f not in FACTORED:
+        return d, None
+    A, Bm, C = _fac_A(t, f), t.fac["B"], t.fac["C"]
+    brows, parts = _fac_trace_parts(t, f, rows)
+    c = st
+    for xl, ins in parts:
+        c += _in_cost(g, f, k, len(ins)) + int(np.count_nonzero(A[np.ix_(xl, ins)]))
+        c += int(np.count_nonzero(Bm[np.ix_(brows, xl)]))
+    if f == 0:
+        c += int(np.count_nonzero(C[np.ix_(rows, brows)]))
+    return d, c
+
+
+def _trace_factored(t, g, f, k, rows):
+    d, c = _trace_costs(t, g, f, k, rows)
+    return c is not None and c < d
+
+
+def _trace_job_cost(t, g, f, k, rows):
+    d, c = _trace_costs(t, g, f, k, rows)
+    return d if c is None else min(d, c)
+
+
+def _fac_lift_parts(t, f, rows):
+    """Dependencies of the factored lift of face f into volume rows `rows`: (needed
+    intermediates, collapsed-basis face rows).  Face 0's jumps are converted to the
+    collapsed basis once per element (stage C2), so both faces read them directly."""
+    A, Bm = _fac_A(t, f), t.fac["B"]
+    xs = sorted({int(x) for r in rows for x in np.nonzero(A[:, r])[0]})
+    brows = sorted({int(c) for x in xs for c in np.nonzero(Bm[:, x])[0]})
+    return xs, brows
+
+
+def _fac_lift_cost(t, Lp, f, rows):
+    A, Bm = _fac_A(t, f), t.fac["B"]
+    rs = set(rows)
+    groups, cur = [], []
+    for blk in _blocks(t):
+        if blk[0] not in rs:
+            continue
+        if cur and len(cur) + len(blk) > LIFT_Y:
+            groups.append(cur)
+            cur = []
+        cur = cur + blk
+    if cur:
+        groups.append(cur)
+    ks = sum(1 for k in range(3) for s_ in range(2) if Lp[f][k][s_] != 0.0)
+    c = ks * len(rows)
+    for grows in groups:
+        xs, brows = _fac_lift_parts(t, f, grows)
+        c += (2 * len(brows) + 2 * int(np.count_nonzero(Bm[np.ix_(brows, xs)]))
+              + 2 * int(np.count_nonzero(A[np.ix_(xs, grows)])))
+    return c
+
+
+def _direct_lift_cost(t, Lp, f, rows):
+    ks = sum(1 for k in range(3) if np.any(Lp[f][k] != 0))
+    sub = t.T[f][:, rows]
+    nm = int(np.count_nonzero(np.any(sub != 0, axis=1)))
+    nnz = int(np.count_nonzero(sub))
+    per_row = 2 * nnz + 2 * ks * len(rows) if _lift_per_scalar(t, f, rows, Lp) else ks * (nnz + nm)
+    return nm * 4 + per_row
+
+
+def _lift_factored(t, Lp, f, rows):
+    """Face 0 always lifts through the factors (its jumps sit in LDS in the collapsed
+    basis); face 3 does when that is cheaper."""
+    if f == 0:
+        return True
+    return f == 3 and _fac_lift_cost(t, Lp, f, rows) < _direct_lift_cost(t, Lp, f, rows)
+
+
 def _lift_per_scalar(t, f, rows, Lp):
     """Lift the two jumps separately (2 nnz + combine) when cheaper than one lift per
     component that face f reaches (one nnz each)."""
@@ -106,20 +238,10 @@ def _lift_per_scalar(t, f, rows, Lp):
     return 2 * nnz + 2 * ncomp * len(rows) < ncomp * nnz
 
 
-def _trace_job_cost(t, g, f, rows):
-    """Instruction estimate of a staged trace job: per streamed mode the LDS loads of
-    the components face f needs and the two tangential conversions, then two FMAs
-    per trace-table entry, and the stores of the traces."""
-    comps = sum(1 for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0)
-    conv = sum(1 for k in range(2) for c in range(3) if g[f][k][c] != 0.0)
-    cols = np.any(t.T[f][rows] != 0, axis=0)
-    return int(np.count_nonzero(cols) * (comps + conv + 2) + 2 * np.count_nonzero(t.T[f][rows]) + 2 * len(rows))
-
-
 def _out_job_cost(t, Lp, rows):
     """Instruction estimate of an output job: per streamed mode the LDS loads of the
-    needed derivative-frame components and the curl FMAs; per face mode touched two
-    jump loads and the lift FMAs; the load-FMA-store update of 3 rows each."""
+    needed derivative-frame components and the curl FMAs; per face the lift (direct
+    table or collapsed factors); the load-FMA-store update of 3 rows each."""
     c = 0
     for a in range(t.N):
         hits = [[b for b in rows if t.D[d][b, a] != 0] for d in range(3)]
@@ -134,12 +256,7 @@ def _out_job_cost(t, Lp, rows):
                 need.add(i)
         c += len(need) + 2 + sum(2 * len(h) for h in hits)
     for f in range(4):
-        ks = sum(1 for k in range(3) if np.any(Lp[f][k] != 0))
-        sub = t.T[f][:, rows]
-        nm = int(np.count_nonzero(np.any(sub != 0, axis=1)))
-        nnz = int(np.count_nonzero(sub))
-        per_row = 2 * nnz + 2 * ks * len(rows) if _lift_per_scalar(t, f, rows, Lp) else ks * (nnz + nm)
-        c += nm * 4 + per_row
+        c += _fac_lift_cost(t, Lp, f, rows) if _lift_factored(t, Lp, f, rows) else _direct_lift_cost(t, Lp, f, rows)
     return c + 9 * len(rows)
 
 
@@ -186,91 +303,91 @@ def _balance(items, single, bin_cost, nw, cap, sweeps=4):
 
 
 def _plan_traces(t, g, nw):
-    """Trace jobs: every face is cut into s_f contiguous runs of quads (four face
-    modes, one 16-byte store per tangent), the runs are spread over the waves
-    longest first, and the cut (s_0..s_3) with the smallest largest wave load is
-    kept (fewest jobs on ties).  Few jobs per face keep the re-streaming of the
-    staged field (LDS reads and frame conversions) low."""
+    """Trace jobs: one per (face, tangent) -- the job streams the staged field once
+    for all face rows of that tangent -- cut into s contiguous runs of quads (four
+    face modes, one 16-byte store) where that balances the waves better.  The cut
+    counts minimising (largest wave load + mean wave load) are kept; runs go to the
+    waves longest first."""
     import itertools
 
     NF = t.NF
     NQ = (NF + 3) // 4
+    units = [(f, k) for f in range(4) for k in range(2)]
     rows_of = lambda i, j: list(range(4 * i, min(NF, 4 * j)))
-    cost = [[[0] * (NQ + 1) for _ in range(NQ + 1)] for _ in range(4)]
-    for f in range(4):
-        for i in range(NQ):
-            for j in range(i + 1, NQ + 1):
-                cost[f][i][j] = _trace_job_cost(t, g, f, rows_of(i, j)) if len(rows_of(i, j)) <= TRACE_ROWS else 10 ** 9
+    cap = 2 * TRACE_ROWS
+    memo = {}
 
-    def cuts(f, s_f):
-        """Contiguous runs of face f's quads minimising the largest run cost (DP)."""
+    def cost(u, i, j):
+        key = (u, i, j)
+        if key not in memo:
+            r = rows_of(i, j)
+            memo[key] = _trace_job_cost(t, g, u[0], u[1], r) if len(r) <= cap else 10 ** 9
+        return memo[key]
+
+    def cuts(u, s_u):
         INF = 10 ** 18
-        best = [[INF] * (NQ + 1) for _ in range(s_f + 1)]
-        arg = [[0] * (NQ + 1) for _ in range(s_f + 1)]
+        best = [[INF] * (NQ + 1) for _ in range(s_u + 1)]
+        arg = [[0] * (NQ + 1) for _ in range(s_u + 1)]
         best[0][0] = 0
-        for r in range(1, s_f + 1):
+        for r in range(1, s_u + 1):
             for j in range(1, NQ + 1):
                 for i in range(r - 1, j):
-                    v = max(best[r - 1][i], cost[f][i][j])
+                    v = max(best[r - 1][i], cost(u, i, j))
                     if v < best[r][j]:
                         best[r][j], arg[r][j] = v, i
         out, j = [], NQ
-        for r in range(s_f, 0, -1):
+        for r in range(s_u, 0, -1):
             i = arg[r][j]
             out.append((i, j))
             j = i
         return out[::-1]
 
-    runs = {(f, s_f): cuts(f, s_f) for f in range(4) for s_f in range(1, min(nw, NQ) + 1)}
+    smax = min(NQ, 3 if nw > 8 else 2)
+    runs = {(u, s_u): cuts(u, s_u) for u in units for s_u in range(1, smax + 1)}
     best = None
-    for split in itertools.product(range(1, min(nw, NQ) + 1), repeat=4):
-        if sum(split) > 2 * nw:
-            continue
-        jobs = [(cost[f][i][j], f, i, j) for f in range(4) for i, j in runs[(f, split[f])]]
+    for split in itertools.product(range(1, smax + 1), repeat=len(units)):
+        jobs = [(cost(u, i, j), u, i, j) for u, s_u in zip(units, split) for i, j in runs[(u, s_u)]]
         load = [0] * nw
         assign = [[] for _ in range(nw)]
-        for c, f, i, j in sorted(jobs, reverse=True):
+        for c, u, i, j in sorted(jobs, reverse=True):
             w = min(range(nw), key=lambda w: load[w])
             load[w] += c
-            assign[w].append((f, rows_of(i, j)))
-        key = (max(load), len(jobs))
+            assign[w].append((u[0], u[1], rows_of(i, j)))
+        key = (max(load) + sum(load) / nw, len(jobs))
         if best is None or key < best[0]:
             best = (key, assign, load)
     _, assign, load = best
-    out = []
-    for w, jobs in enumerate(assign):
-        # two runs of one face on one wave: one stream if the accumulators allow
-        by_f = {}
-        for f, rows in jobs:
-            by_f.setdefault(f, []).append(rows)
-        merged = []
-        for f, runs_f in sorted(by_f.items()):
-            cur = []
-            for rows in sorted(runs_f):
-                if cur and len(cur) + len(rows) > TRACE_ROWS:
-                    merged.append((f, cur))
-                    cur = []
-                cur = sorted(cur + rows)
-            merged.append((f, cur))
-        out.append(merged)
-        load[w] = sum(_trace_job_cost(t, g, f, rows) for f, rows in merged)
-    return out, load
+    return [sorted(a) for a in assign], load
+
+
+def _plan_c2(t, nw):
+    """Stage C2 tasks (degree n, scalar s): face 0's jumps of degree n converted in
+    place from psi to the collapsed basis (C^T), spread over the waves by cost."""
+    tasks = sorted(((n + 1) ** 2, n, s_) for n in range(t.p + 1) for s_ in range(2))[::-1]
+    load = [0] * nw
+    out = [[] for _ in range(nw)]
+    for c, n, s_ in tasks:
+        w = min(range(nw), key=lambda w: load[w])
+        load[w] += c
+        out[w].append((n, s_))
+    return out
 
 
 def plan(p: int, nw: int):
-    """One output job per wave (volume rows, all three components) and per wave one
-    trace job per face it touches (face rows), balanced over the nw waves with the
-    instruction estimates above: every job streams its operands from LDS once, so
-    few large jobs keep the LDS traffic low."""
+    """One output job per wave (volume rows, all three components; unions of (m, k)
+    blocks, the unit of the factored lift) and the trace jobs above, balanced over
+    the nw waves with the instruction estimates above."""
     t = TB.build(p)
-    N, NF = t.N, t.NF
     g, Lp = TB.face_weights(t)
-
     tr_w, tr_load = _plan_traces(t, g, nw)
-    ob, out_load = _balance(list(range(N)), lambda b: _out_job_cost(t, Lp, [b]),
-                            lambda rows: _out_job_cost(t, Lp, sorted(rows)), nw, lambda rows: len(rows) <= OUT_ROWS)
-    out_w = [[sorted(rows)] if rows else [] for rows in ob]
-    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load)
+    blks = [tuple(b) for b in _blocks(t)]
+    rows_of = lambda bl: sorted(r for b in bl for r in b)
+    cap = out_rows_cap(p)
+    ob, out_load = _balance(blks, lambda b: _out_job_cost(t, Lp, list(b)),
+                            lambda bl: _out_job_cost(t, Lp, rows_of(bl)), nw,
+                            lambda bl: len(rows_of(bl)) <= cap)
+    out_w = [[rows_of(bl)] if bl else [] for bl in ob]
+    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load, c2=_plan_c2(t, nw))
 
 
 def trace_strides(NF: int):
@@ -285,44 +402,109 @@ def trace_strides(NF: int):
     return FS, 4 * FS
 
 
-def _trace_job(a_, t, g, f, rows, ind):
-    """Tangential traces tau_k = g_fk . w on face f, face rows `rows` (whole quads of
+def _lin(terms):
+    """Expression of a linear combination [(coef, name)] with literal coefficients."""
+    out = []
+    for c, v in terms:
+        if c == 1.0:
+            out.append(f"+ {v}")
+        elif c == -1.0:
+            out.append(f"- {v}")
+        else:
+            out.append(f"+ {_lit(c)} * {v}")
+    e = " ".join(out)
+    return e[2:] if e.startswith("+ ") else "-" + e[2:]
+
+
+def _tangent_input(g, f, k, x):
+    """(expression statements, scale, name): the tangential scalar of one streamed
+    mode from its loaded components x; a single-component tangent is not formed,
+    its weight is folded into the operator coefficients instead."""
+    terms = _tangent_terms(g, f, k)
+    if len(terms) == 1:
+        return [], terms[0][1], x[0]
+    return [("q", _lin([(w, v) for (c, w), v in zip(terms, x)]))], 1.0, "q"
+
+
+def _trace_job(a_, t, g, f, k, rows, ind):
+    """Tangential trace tau_k = g_fk . w on face f, face rows `rows` (whole quads of
     four face modes), of the field staged in LDS (derivative frame), stored to the
-    tile's block of Tout with one 16-byte store per lane, tangent and quad."""
-    N, NF = t.N, t.NF
-    FS, ES = trace_strides(NF)
-    NFP, FQ = FS // 2, FS // 4
+    tile's block of Tout with one 16-byte store per lane and quad.  Faces 0 and 3 go
+    through the collapsed tensor-product factors when that is cheaper: per (m, k)
+    block the inputs are transformed by A into intermediates, which B scatters into
+    the face rows (on face 0 rows of the collapsed basis, mapped to psi by C at the
+    end)."""
+    N = t.N
+    comps = [c for c, _ in _tangent_terms(g, f, k)]
+    loads = lambda a: [f"wl[({c * N + a}) * {LANES} + lane]" for c in comps]
     a_(ind + "{")
-    a_(ind + "  R " + ", ".join(f"ts{k}_{m} = R(0)" for m in rows for k in range(2)) + ";")
     blocks = []
-    for a in range(N):
-        ms = [m for m in rows if t.T[f][m, a] != 0]
-        if not ms:
-            continue
-        comps = [c for c in range(3) if g[f][0][c] != 0.0 or g[f][1][c] != 0.0]
+    if _trace_factored(t, g, f, k, rows):
+        A, Bm, C = _fac_A(t, f), t.fac["B"], t.fac["C"]
+        brows, parts = _fac_trace_parts(t, f, rows)
+        acc = (lambda c: f"tc_{c}") if f == 0 else (lambda c: f"ts_{c}")
+        a_(ind + "  R " + ", ".join(f"{acc(c)} = R(0)" for c in brows) + ";")
+        for xl, ins in parts:
+            def body(x, xl=xl, ins=ins):
+                out, names, sc = [], [], 1.0
+                for n, a in enumerate(ins):
+                    pre, sc, nm = _tangent_input(g, f, k, x[n * len(comps):(n + 1) * len(comps)])
+                    for v, e in pre:
+                        out.append(f"const R {v}{n} = {e};")
+                        nm = f"{v}{n}"
+                    names.append(nm)
+                for xi in xl:
+                    out.append(f"const R y_{xi} = " + _lin([(sc * A[xi, a], names[n]) for n, a in enumerate(ins)
+                                                            if A[xi, a] != 0.0]) + ";")
+                for xi in xl:
+                    for c in brows:
+                        if Bm[c, xi] != 0.0:
+                            out.append(_fma(acc(c), Bm[c, xi], f"y_{xi}"))
+                return out
+            blocks.append(([l for a in ins for l in loads(a)], body))
+        a_(ind + "  {")
+        _Stream(a_, ind + "    ", "pf").emit(blocks)
+        a_(ind + "  }")
+        if f == 0:
+            a_(ind + "  // change of face basis (collapsed towards the first vertex -> psi), per quad")
+            for mq in sorted({m // 4 for m in rows}):
+                ms = [m for m in range(4 * mq, 4 * mq + 4) if m in rows]
+                a_(ind + "  {")
+                for m in ms:
+                    a_(ind + f"    const R ts_{m} = " + _lin([(C[m, c], f"tc_{c}") for c in brows if C[m, c] != 0.0]) + ";")
+                _trace_stores(a_, t, f, k, ms, ind + "  ")
+                a_(ind + "  }")
+            a_(ind + "}")
+            return
+    else:
+        T = t.T[f]
+        a_(ind + "  R " + ", ".join(f"ts_{m} = R(0)" for m in rows) + ";")
+        for a in range(N):
+            ms = [m for m in rows if T[m, a] != 0]
+            if not ms:
+                continue
 
-        def body(x, a=a, ms=ms, comps=comps):
-            xs = dict(zip(comps, x))
-            out = []
-            for k in range(2):
-                terms = [(g[f][k][c], xs[c]) for c in comps if g[f][k][c] != 0.0]
-                out.append(f"const R q{k} = " + " + ".join(
-                    (v if c == 1.0 else (f"-{v}" if c == -1.0 else f"{_lit(c)} * {v}")) for c, v in terms) + ";")
-            for m in ms:
-                for k in range(2):
-                    out.append(_fma(f"ts{k}_{m}", t.T[f][m, a], f"q{k}"))
-            return out
-
-        blocks.append(([f"wl[({c * N + a}) * {LANES} + lane]" for c in comps], body))
-    a_(ind + "  {")
-    _Stream(a_, ind + "    ", "pf").emit(blocks)
-    a_(ind + "  }")
-    for mq in sorted({m // 4 for m in rows}):
-        for k in range(2):
-            vals = [f"ts{k}_{m}" if m in rows else "R(0)" for m in range(4 * mq, 4 * mq + 4)]
-            chunk = f * FQ + (k * NFP + 4 * mq) // 4
-            a_(ind + f"  store4s<ST>(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
+            def body(x, a=a, ms=ms):
+                pre, sc, nm = _tangent_input(g, f, k, x)
+                out = [f"const R {v} = {e};" for v, e in pre]
+                for m in ms:
+                    out.append(_fma(f"ts_{m}", sc * T[m, a], nm))
+                return out
+            blocks.append((loads(a), body))
+        a_(ind + "  {")
+        _Stream(a_, ind + "    ", "pf").emit(blocks)
+        a_(ind + "  }")
+    _trace_stores(a_, t, f, k, rows, ind)
     a_(ind + "}")
+
+
+def _trace_stores(a_, t, f, k, rows, ind):
+    FS, ES = trace_strides(t.NF)
+    NFP, FQ = FS // 2, FS // 4
+    for mq in sorted({m // 4 for m in rows}):
+        vals = [f"ts_{m}" if m in rows else "R(0)" for m in range(4 * mq, 4 * mq + 4)]
+        chunk = f * FQ + (k * NFP + 4 * mq) // 4
+        a_(ind + f"  store4s<ST>(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
 
 
 def _curl_job(a_, t, rows, ind):
@@ -360,6 +542,62 @@ def _curl_job(a_, t, rows, ind):
     a_(ind + "}")
 
 
+
+LIFT_Y = 8  # intermediates per scalar held at once by a factored lift (bounds its registers)
+
+
+def _lift_face_fac(a_, t, Lp, f, rows, jd, ind):
+    """Lift of face f's two jumps into the job's rows through the transposed
+    collapsed tensor-product factors: B^T from the collapsed-basis face rows (face
+    3: psi itself; face 0: the rows stage C2 converted) into the intermediates y_s,
+    A^T into the rows, then the stored-frame map Lp_f of the two scalars into the
+    three components.  The job's (m, k) blocks are taken in groups of at most LIFT_Y
+    intermediates, each group streaming the face rows it needs."""
+    A, Bm = _fac_A(t, f), t.fac["B"]
+    pos = {b: j for j, b in enumerate(rows)}
+    groups, cur = [], []
+    for blk in _blocks(t):
+        if blk[0] not in pos:
+            continue
+        if cur and len(cur) + len(blk) > LIFT_Y:
+            groups.append(cur)
+            cur = []
+        cur = cur + blk
+    if cur:
+        groups.append(cur)
+    a_(ind + f"  {{  // face {f}, collapsed tensor-product factors")
+    for grows in groups:
+        xs, brows = _fac_lift_parts(t, f, grows)
+        a_(ind + "    {")
+        a_(ind + "      R " + ", ".join(f"y{s_}_{x} = R(0)" for x in xs for s_ in range(2)) + ";")
+        blocks = []
+        for c in brows:
+            def body(x, c=c, xs=xs):
+                out = []
+                for xi in xs:
+                    if Bm[c, xi] != 0.0:
+                        for s_ in range(2):
+                            out.append(_fma(f"y{s_}_{xi}", Bm[c, xi], x[s_]))
+                return out
+            blocks.append(([jd(f, 0, c), jd(f, 1, c)], body))
+        a_(ind + "      {")
+        _Stream(a_, ind + "        ", "pj").emit(blocks)
+        a_(ind + "      }")
+        for b in grows:
+            j = pos[b]
+            terms = [(A[xi, b], xi) for xi in xs if A[xi, b] != 0.0]
+            if not terms:
+                continue
+            for s_ in range(2):
+                a_(ind + f"      const R l{s_}_{j} = " + _lin([(c, f"y{s_}_{xi}") for c, xi in terms]) + ";")
+            for k in range(3):
+                for s_ in range(2):
+                    if Lp[f][k][s_] != 0.0:
+                        a_(ind + "      " + _fma(f"acc{k}_{j}", Lp[f][k][s_], f"l{s_}_{j}"))
+        a_(ind + "    }")
+    a_(ind + "  }")
+
+
 def _lift_job(a_, t, Lp, rows, ind):
     """Lifted jumps (from LDS) added to the rates of the wave's rows, face by face,
     then the update V = V_old + sdt * rate of the three components (old values
@@ -373,6 +611,9 @@ def _lift_job(a_, t, Lp, rows, ind):
             a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = ldf<ST>(&V[({k * N + b}) * Ks + el])" for k in range(3)) + ";")
     jd = lambda f, k, m: f"wl[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
     for f in range(4):
+        if _lift_factored(t, Lp, f, rows):
+            _lift_face_fac(a_, t, Lp, f, rows, jd, ind)
+            continue
         ks = [k for k in range(3) if np.any(Lp[f][k] != 0)]
         ms = [m for m in range(NF) if np.any(t.T[f][m, rows] != 0)]
         if not ks or not ms:
@@ -451,6 +692,14 @@ def waves_for(p: int) -> int:
 
 def vo_early(p: int) -> bool:
     return LAUNCH[p][1] if p in LAUNCH else True
+
+
+def out_rows_cap(p: int) -> int:
+    """Volume rows per output job: OUT_ROWS, or 12 where the launch leaves a lane 128
+    registers (four waves per SIMD), so that the rows' accumulators, a factored lift's
+    intermediates and a stream group fit without spilling."""
+    waves_per_simd = max(1, waves_for(p) * groups_per_cu(p, 4) // 4)
+    return 12 if 512 // waves_per_simd <= 128 else OUT_ROWS
 
 
 def groups_per_cu(p: int, elem_bytes: int) -> int:
@@ -537,14 +786,35 @@ def _jump_lines(t, nw):
     return L
 
 
+def _c2_stage(a_, t, pl, nw):
+    """Stage C2: face 0's jump rows of each degree n (both scalars) replaced by their
+    coordinates in the collapsed face basis, C^T J (C only mixes equal degrees)."""
+    C = t.fac["C"]
+    NF = t.NF
+    fdeg = [a + b for (a, b) in t.fmodes]
+    for w in range(nw):
+        if not pl["c2"][w]:
+            continue
+        a_(f"  if (wave == {w}) {{")
+        for n, s_ in pl["c2"][w]:
+            rs = [r for r in range(NF) if fdeg[r] == n]
+            assert np.all(C[np.ix_([r for r in range(NF) if fdeg[r] != n], rs)] == 0.0)
+            a_("    {")
+            a_("      const R " + ", ".join(f"j{r} = wl[({s_ * NF + r}) * {LANES} + lane]" for r in rs) + ";")
+            for c in rs:
+                a_(f"      wl[({s_ * NF + c}) * {LANES} + lane] = " + _lin([(C[r, c], f"j{r}") for r in rs if C[r, c] != 0.0]) + ";")
+            a_("    }")
+        a_("  }")
+
+
 def _trace_stage(a_, t, g, pl, nw):
     """Trace jobs of the field staged in LDS, stored straight to the tile's block."""
     a_(f"  const size_t tb = (size_t)tile * {LANES * trace_strides(t.NF)[1]};")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
-        for (f, rows) in pl["trace"][w]:
-            a_(f"    // face {f}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, rows, "    ")
+        for (f, k, rows) in pl["trace"][w]:
+            a_(f"    // face {f}, tangent {k}, face modes {rows[0]}..{rows[-1]}")
+            _trace_job(a_, t, g, f, k, rows, "    ")
         a_("  }")
 
 
@@ -575,6 +845,9 @@ def _phase_body(a_, t, g, Lp, pl, nw):
     for l in _jump_lines(t, nw):
         a_("    " + l)
     a_("  }")
+    a_("  __syncthreads();")
+    a_("  // C2: face 0's jumps from psi to the collapsed basis of the lift factors, in place")
+    _c2_stage(a_, t, pl, nw)
     a_("  __syncthreads();")
     a_("  // D: lifted jumps and the component-separable update of V")
     for w in range(nw):

@@ -15,9 +15,18 @@ orthonormal degree-major Dubiner basis (gen/basis.py):
 * trace operators  T_f[m, a] = int_{unit triangle} psi_m(s,t) phi_a(xhat_f(s,t)) ds dt
   for the four faces in the sorted-vertex parametrisation
   xhat_f(s,t) = w0 + s (w1 - w0) + t (w2 - w0), (w0, w1, w2) the face's vertices
-  in increasing local index (Section 3.2.3 evaluates traces modally through the
-  tensor-product structure; T_0 is a signed sum over k, the others are sparse
-  tables).  T_f^T is the lift used by the face flux.
+  in increasing local index.  T_f^T is the lift used by the face flux.
+  Densities at p = 6: 1572 (slanted face 0), 84 (x = 0, a signed sum over the
+  x index k), 336 (y = 0) and 1320 (z = 0) of 2352 entries.
+* the collapsed tensor-product factorisation of the two dense traces
+  (Section 3.2.3: traces in O(N) through the tensor-product structure), see
+  ``factors``: T_3 = B A_3 and T_0 = C B A_0 with A block-diagonal over
+  (m, k) = (i + j, k) (a Legendre transform in the inner collapsed
+  coordinate), B block-diagonal over the face index a (a Jacobi re-expansion
+  in the outer one) and C block-diagonal over the face degree (the change
+  between the two orthonormal face bases collapsed at different vertices):
+  666 and 804 multiply-adds per scalar at p = 6 instead of 1320 and 1572;
+  the y = 0 trace is B itself up to a column scaling (336).
 * the face frames: reference edge tangents t1 = w1 - w0, t2 = w2 - w0, the
   scaled outer normals n_f (unit-triangle measure) and the 3x2 map L_f with
   n_f x a = L_f (a.t1, a.t2)  for any vector a.
@@ -100,7 +109,60 @@ def build(p: int) -> Tables:
         t.normal.append(n)
         t.L.append(L)
     t.frame = frame()
+    t.fac = factors(t)
+    for f, prod in ((3, t.fac["B"] @ t.fac["A3"]), (0, t.fac["C"] @ t.fac["B"] @ t.fac["A0"])):
+        if np.abs(prod - t.T[f]).max() > 1e-12:
+            raise AssertionError(f"trace factors of face {f} do not reproduce T{f}")
     return t
+
+
+def factors(t: Tables):
+    """Collapsed tensor-product factors of the face-0 and face-3 traces.
+
+    On z = 0 (face 3, points (s, t, 0)) and, after the barycentric relabelling
+    (s, t) -> (1 - s - t, s), on the slanted face 0 (points (1 - s - t, s, t)) the
+    restriction of phi_ijk separates as
+        sqrt((2i+1)(2m+2)) sigma_i ((1-eta)/2)^i P_j^{(2i+1,0)}(eta)
+          * (1-s)^m P_k^{(2m+2,0)}(2s-1) sqrt(2m+2k+3),      m = i + j,
+    with sigma_i = (-1)^i on z = 0 (the innermost factor at c = -1) and 1 on
+    the slanted face (c = +1).  Expanding the eta factor in orthonormal Legendre
+    polynomials gives the intermediate coefficients X[(a,m,k)] = A[(a,m,k), (i,j,k)]
+    u[(i,j,k)] (a <= m); each intermediate function
+        Lambda_amk = Phat_a(eta) (1-s)^m P_k^{(2m+2,0)}(2s-1) sqrt(2m+2k+3)
+    projects onto the face modes (a, b) of the same a only (B).  On face 0 the
+    result is in the face basis collapsed towards the face's first vertex,
+    chi_ab(s, t) = psi_ab(1 - s - t, s); C maps it to psi and mixes only modes of
+    equal degree a + b.  Returns dict(X = [(a, m, k)], A3, A0, B, C) with exact
+    zeros; ``build`` checks B A3 = T_3 and C B A0 = T_0 to 1e-12.
+    """
+    from scipy.special import eval_jacobi, roots_legendre
+
+    p = t.p
+    idx = {m: r for r, m in enumerate(t.modes)}
+    X = [(a, m, k) for m in range(p + 1) for k in range(p - m + 1) for a in range(m + 1)]
+    xidx = {v: r for r, v in enumerate(X)}
+    xe, we = roots_legendre(p + 2)
+    phat = lambda a, x: np.sqrt((2 * a + 1) / 2.0) * eval_jacobi(a, 0, 0, x)
+    A3 = np.zeros((len(X), t.N))
+    A0 = np.zeros((len(X), t.N))
+    for (i, j, k) in t.modes:
+        m = i + j
+        f = np.sqrt((2 * i + 1) * (2 * m + 2)) * ((1 - xe) / 2) ** i * eval_jacobi(j, 2 * i + 1, 0, xe)
+        for a in range(m + 1):
+            v = float(np.sum(we * phat(a, xe) * f))
+            A0[xidx[(a, m, k)], idx[(i, j, k)]] = v
+            A3[xidx[(a, m, k)], idx[(i, j, k)]] = v * (-1) ** i
+    st, wt = B.collapsed_rule_tri(p + 2)
+    s, tt = st[:, 0], st[:, 1]
+    os_ = 1.0 - s
+    eta = np.where(os_ > 1e-300, 2 * tt / np.where(os_ > 1e-300, os_, 1) - 1, -1.0)
+    lam = np.empty((len(X), len(s)))
+    for r, (a, m, k) in enumerate(X):
+        lam[r] = phat(a, eta) * os_ ** m * eval_jacobi(k, 2 * m + 2, 0, 2 * s - 1) * np.sqrt(2 * m + 2 * k + 3)
+    Vf = B.face_values(p, st)
+    Bm = (Vf * wt) @ lam.T
+    C = (Vf * wt) @ B.face_values(p, np.stack([1.0 - s - tt, s], 1)).T
+    return dict(X=X, A3=_clean(A3, "A3"), A0=_clean(A0, "A0"), B=_clean(Bm, "B"), C=_clean(C, "C"))
 
 
 @functools.lru_cache(maxsize=None)

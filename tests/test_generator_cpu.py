@@ -17,17 +17,22 @@ def test_plan_partitions_rows_and_traces(p):
     assert len(pl["out"]) == nw and len(pl["trace"]) == nw
     rows = [b for w in pl["out"] for job in w for b in job]
     assert sorted(rows) == list(range(t.N))
-    assert all(len(job) <= emit.OUT_ROWS for w in pl["out"] for job in w)
-    faces = sorted((f, m) for w in pl["trace"] for f, ms in w for m in ms)
-    assert faces == [(f, m) for f in range(4) for m in range(t.NF)]
+    assert all(len(job) <= emit.out_rows_cap(p) for w in pl["out"] for job in w)
+    traces = sorted((f, k, m) for w in pl["trace"] for f, k, ms in w for m in ms)
+    assert traces == [(f, k, m) for f in range(4) for k in range(2) for m in range(t.NF)]
     for w in pl["trace"]:
-        for f in {f for f, _ in w}:  # one job per face and wave unless its rows do not fit one
-            runs = [ms for g, ms in w if g == f]
-            assert len(runs) == 1 or sum(map(len, runs)) > emit.TRACE_ROWS
-        for f, ms in w:
-            assert len(ms) <= emit.TRACE_ROWS
+        for f, k, ms in w:
+            assert len(ms) <= 2 * emit.TRACE_ROWS
             for q in {m // 4 for m in ms}:  # whole quads (the last one cut at NF)
                 assert set(range(4 * q, min(t.NF, 4 * q + 4))) <= set(ms)
+    # output jobs are unions of whole (m, k) blocks; every stage-C2 task appears once
+    blk = {r: i for i, b in enumerate(emit._blocks(t)) for r in b}
+    for w in pl["out"]:
+        for job in w:
+            for r in job:
+                assert all(q in job for q, i in blk.items() if i == blk[r])
+    c2 = sorted(x for w in pl["c2"] for x in w)
+    assert c2 == [(n, s) for n in range(p + 1) for s in range(2)]
 
 
 @pytest.mark.parametrize("p", range(1, TB.P_MAX + 1))
