@@ -107,6 +107,12 @@ CYC = {0: (1, 2), 1: (2, 0), 2: (0, 1)}
 
 
 FACTORED = (0, 3)  # faces whose trace goes through the collapsed tensor-product factors
+# Faces whose own traces a phase recomputes from the staged field (cheap: the x = 0 face is
+# a signed sum, y = 0 one factor); the phase that updates a field writes their traces only
+# where the neighbour is in another tile.  The other faces' traces are written for every
+# element and read back as the element's own traces; in-tile neighbours are read from LDS.
+RECOMPUTED = (1, 2)
+READ = (0, 3)
 
 
 def _blocks(t):
@@ -242,6 +248,13 @@ def _out_job_cost(t, Lp, rows):
     """Instruction estimate of an output job: per streamed mode the LDS loads of the
     needed derivative-frame components and the curl FMAs; per face the lift (direct
     table or collapsed factors); the load-FMA-store update of 3 rows each."""
+    c = _curl_cost(t, rows)
+    for f in range(4):
+        c += _fac_lift_cost(t, Lp, f, rows) if _lift_factored(t, Lp, f, rows) else _direct_lift_cost(t, Lp, f, rows)
+    return c + 9 * len(rows)
+
+
+def _curl_cost(t, rows):
     c = 0
     for a in range(t.N):
         hits = [[b for b in rows if t.D[d][b, a] != 0] for d in range(3)]
@@ -255,9 +268,7 @@ def _out_job_cost(t, Lp, rows):
             if hits[j]:
                 need.add(i)
         c += len(need) + 2 + sum(2 * len(h) for h in hits)
-    for f in range(4):
-        c += _fac_lift_cost(t, Lp, f, rows) if _lift_factored(t, Lp, f, rows) else _direct_lift_cost(t, Lp, f, rows)
-    return c + 9 * len(rows)
+    return c
 
 
 def _balance(items, single, bin_cost, nw, cap, sweeps=4):
@@ -302,7 +313,7 @@ def _balance(items, single, bin_cost, nw, cap, sweeps=4):
     return bins, load
 
 
-def _plan_traces(t, g, nw):
+def _plan_traces(t, g, nw, faces=(0, 1, 2, 3), init=None):
     """Trace jobs: one per (face, tangent) -- the job streams the staged field once
     for all face rows of that tangent -- cut into s contiguous runs of quads (four
     face modes, one 16-byte store) where that balances the waves better.  The cut
@@ -312,7 +323,7 @@ def _plan_traces(t, g, nw):
 
     NF = t.NF
     NQ = (NF + 3) // 4
-    units = [(f, k) for f in range(4) for k in range(2)]
+    units = [(f, k) for f in faces for k in range(2)]
     rows_of = lambda i, j: list(range(4 * i, min(NF, 4 * j)))
     cap = 2 * TRACE_ROWS
     memo = {}
@@ -342,12 +353,12 @@ def _plan_traces(t, g, nw):
             j = i
         return out[::-1]
 
-    smax = min(NQ, 3 if nw > 8 else 2)
+    smax = min(NQ, max(1, min(3 if nw > 8 else 2, (2 * nw) // len(units))))
     runs = {(u, s_u): cuts(u, s_u) for u in units for s_u in range(1, smax + 1)}
     best = None
     for split in itertools.product(range(1, smax + 1), repeat=len(units)):
         jobs = [(cost(u, i, j), u, i, j) for u, s_u in zip(units, split) for i, j in runs[(u, s_u)]]
-        load = [0] * nw
+        load = list(init) if init else [0] * nw
         assign = [[] for _ in range(nw)]
         for c, u, i, j in sorted(jobs, reverse=True):
             w = min(range(nw), key=lambda w: load[w])
@@ -387,7 +398,11 @@ def plan(p: int, nw: int):
                             lambda bl: _out_job_cost(t, Lp, rows_of(bl)), nw,
                             lambda bl: len(rows_of(bl)) <= cap)
     out_w = [[rows_of(bl)] if bl else [] for bl in ob]
-    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load, c2=_plan_c2(t, nw))
+    # the own-trace jobs share a barrier interval with the curl: balance them together
+    curl = [sum(_curl_cost(t, rows) for rows in w) for w in out_w]
+    own_w, own_load = _plan_traces(t, g, nw, RECOMPUTED, init=curl)
+    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load, c2=_plan_c2(t, nw),
+                own=own_w, own_load=own_load)
 
 
 def trace_strides(NF: int):
@@ -426,7 +441,7 @@ def _tangent_input(g, f, k, x):
     return [("q", _lin([(w, v) for (c, w), v in zip(terms, x)]))], 1.0, "q"
 
 
-def _trace_job(a_, t, g, f, k, rows, ind):
+def _trace_job(a_, t, g, f, k, rows, ind, sink=None):
     """Tangential trace tau_k = g_fk . w on face f, face rows `rows` (whole quads of
     four face modes), of the field staged in LDS (derivative frame), stored to the
     tile's block of Tout with one 16-byte store per lane and quad.  Faces 0 and 3 go
@@ -435,6 +450,7 @@ def _trace_job(a_, t, g, f, k, rows, ind):
     the face rows (on face 0 rows of the collapsed basis, mapped to psi by C at the
     end)."""
     N = t.N
+    sink = sink or (lambda a_, ms, ind: _trace_stores(a_, t, f, k, ms, ind))
     comps = [c for c, _ in _tangent_terms(g, f, k)]
     loads = lambda a: [f"wl[({c * N + a}) * {LANES} + lane]" for c in comps]
     a_(ind + "{")
@@ -472,7 +488,7 @@ def _trace_job(a_, t, g, f, k, rows, ind):
                 a_(ind + "  {")
                 for m in ms:
                     a_(ind + f"    const R ts_{m} = " + _lin([(C[m, c], f"tc_{c}") for c in brows if C[m, c] != 0.0]) + ";")
-                _trace_stores(a_, t, f, k, ms, ind + "  ")
+                sink(a_, ms, ind + "  ")
                 a_(ind + "  }")
             a_(ind + "}")
             return
@@ -494,17 +510,20 @@ def _trace_job(a_, t, g, f, k, rows, ind):
         a_(ind + "  {")
         _Stream(a_, ind + "    ", "pf").emit(blocks)
         a_(ind + "  }")
-    _trace_stores(a_, t, f, k, rows, ind)
+    sink(a_, rows, ind)
     a_(ind + "}")
 
 
-def _trace_stores(a_, t, f, k, rows, ind):
+def _trace_stores(a_, t, f, k, rows, ind, pred=None):
+    """16-byte stores of the quads of `rows` to the tile's block of Tout (only lanes with
+    `pred`, if given)."""
     FS, ES = trace_strides(t.NF)
     NFP, FQ = FS // 2, FS // 4
     for mq in sorted({m // 4 for m in rows}):
         vals = [f"ts_{m}" if m in rows else "R(0)" for m in range(4 * mq, 4 * mq + 4)]
         chunk = f * FQ + (k * NFP + 4 * mq) // 4
-        a_(ind + f"  store4s<ST>(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});")
+        st = f"store4s<ST>(Tout + tb + ({chunk} * {LANES} + lane) * 4, {', '.join(vals)});"
+        a_(ind + ("  " + st if pred is None else f"  if ({pred}) {st}"))
 
 
 def _curl_job(a_, t, rows, ind):
@@ -745,42 +764,48 @@ JUMP_BATCH = 4    # trace chunks per lane loaded before their LDS stores
 
 
 def _jump_lines(t, nw):
-    """Jumps of the tangential traces of U, read from its trace buffer Tin into LDS:
-    neighbour minus own on interior faces, (wall - 1) times own on walls; per lane
-    and chunk one 16-byte load of the own and one of the neighbour's face block.
-    Wave w takes chunks w, w + nw, ...; in rounds of JUMP_BATCH chunks the codes are
-    loaded first, then the trace values (on walls the 'neighbour' load re-reads the
-    own chunk), then the stores.  The last chunk index is clamped; a wave past the
-    end rewrites the last chunk with the same values."""
+    """Jumps of the tangential traces of U (own traces already in LDS, stage T):
+    neighbour minus own on interior faces, (wall - 1) times own on walls.  A neighbour
+    in the same tile is read from LDS, one in another tile from Tin (one 16-byte load
+    of its face block).  Work item (k, j): tangent k, face modes 4j..4j+3 of all four
+    faces; every read of an item's own and neighbour values (same tangent and modes,
+    any face) is made by the wave that then overwrites them with the jumps, so the
+    jumps replace the own traces in place without a barrier.  Wave w takes items w,
+    w + nw, ...; items past the end are skipped (a duplicate would race with the
+    in-place update)."""
     NF = t.NF
     FS, ES = trace_strides(NF)
     NFP, FQ = FS // 2, FS // 4
-    cnt = -(-4 * FQ // nw)
-    L = [f"const size_t own = (size_t)(el >> 6) * {LANES * ES} + (size_t)(el & 63) * 4;",
-         "const R cw = wall - R(1);"]
-    for r0 in range(0, cnt, JUMP_BATCH):
-        idx = range(r0, min(cnt, r0 + JUMP_BATCH))
-        L.append("{")
-        for i in idx:
-            q = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {4 * FQ - 1})"
-            L.append(f"  const int q{i} = {q}, f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
-            L.append(f"  const int code{i} = nbr[f{i} * Ks + el];")
-        for i in idx:
-            L.append(f"  const int nb{i} = code{i} >= 0 ? code{i} >> 2 : el;")
-            L.append(f"  const int gf{i} = code{i} >= 0 ? code{i} & 3 : f{i};")
-            L.append(f"  const R* so{i} = (const R*)__builtin_assume_aligned(Tin + own + (size_t)q{i} * {LANES * 4}, 16);")
-            L.append(f"  const R* sn{i} = (const R*)__builtin_assume_aligned(Tin + (size_t)(nb{i} >> 6) * {LANES * ES} "
-                     f"+ ((size_t)(gf{i} * {FQ} + (q{i} - f{i} * {FQ})) * {LANES} + (nb{i} & 63)) * 4, 16);")
-            L.append(f"  const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
-            L.append(f"  const R t{i}_0 = sn{i}[0], t{i}_1 = sn{i}[1], t{i}_2 = sn{i}[2], t{i}_3 = sn{i}[3];")
-        for i in idx:
-            L.append("  {")
-            L.append(f"    const bool in = code{i} >= 0;")
-            L.append(f"    const int k = c{i} >= {NFP}, m = c{i} - k * {NFP};")
-            L.append(f"    const int d = ((f{i} * 2 + k) * {NF} + m) * {LANES} + lane;")
-            for j in range(4):
-                st = f"wl[d + {j * LANES}] = in ? t{i}_{j} - o{i}_{j} : cw * o{i}_{j};"
-                L.append(f"    {st}" if (j == 0 and NF % 4 == 0) else f"    if (m + {j} < {NF}) {st}")
+    items = [(k, jq) for k in range(2) for jq in range(NFP // 4)]
+    cnt = -(-len(items) // nw)
+    L = ["const R cw = wall - R(1);",
+         "const int code0 = nbr[el], code1 = nbr[Ks + el], code2 = nbr[2 * Ks + el], code3 = nbr[3 * Ks + el];"]
+    for f in range(4):
+        L.append(f"const int nb{f} = code{f} >= 0 ? code{f} >> 2 : el, gf{f} = code{f} >= 0 ? code{f} & 3 : {f};")
+        L.append(f"const bool in{f} = code{f} >= 0 && (nb{f} >> 6) == tile, off{f} = code{f} >= 0 && !in{f};")
+    for i in range(cnt):
+        L.append(f"if (wave + {i * nw} < {len(items)}) {{" if (i + 1) * nw > len(items) else "{")
+        L.append(f"  const int it = wave + {i * nw}, k = it / {NFP // 4}, c = 4 * (it - k * {NFP // 4});")
+        # off-tile neighbour chunks first (one round trip for the four faces)
+        for f in range(4):
+            L.append(f"  R t{f}_0 = R(0), t{f}_1 = R(0), t{f}_2 = R(0), t{f}_3 = R(0);")
+            L.append(f"  if (off{f}) {{")
+            L.append(f"    const R* sn = (const R*)__builtin_assume_aligned(Tin + (size_t)(nb{f} >> 6) * {LANES * ES} "
+                     f"+ ((size_t)(gf{f} * {FQ} + (k * {NFP} + c) / 4) * {LANES} + (nb{f} & 63)) * 4, 16);")
+            L.append(f"    t{f}_0 = sn[0]; t{f}_1 = sn[1]; t{f}_2 = sn[2]; t{f}_3 = sn[3];")
+            L.append("  }")
+        for jj in range(4):
+            if NF % 4:
+                L.append(f"  if (c + {jj} < {NF}) {{")
+            else:
+                L.append("  {")
+            L.append(f"    const int m = c + {jj};")
+            for f in range(4):
+                L.append(f"    const R ow{f} = wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane];")
+                L.append(f"    const R nv{f} = wl[(((gf{f} * 2 + k) * {NF}) + m) * {LANES} + (nb{f} & 63)];")
+            for f in range(4):
+                L.append(f"    wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane] = "
+                         f"code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{f}_{jj}) - ow{f};")
             L.append("  }")
         L.append("}")
     return L
@@ -807,15 +832,84 @@ def _c2_stage(a_, t, pl, nw):
         a_("  }")
 
 
-def _trace_stage(a_, t, g, pl, nw):
-    """Trace jobs of the field staged in LDS, stored straight to the tile's block."""
+def _trace_stage(a_, t, g, pl, nw, masked=True):
+    """Trace jobs of the field staged in LDS, stored straight to the tile's block.  With
+    `masked`, the recomputed faces are stored only by lanes whose neighbour across that
+    face lies in another tile, and their jobs run only in waves that have such a lane."""
     a_(f"  const size_t tb = (size_t)tile * {LANES * trace_strides(t.NF)[1]};")
+    if masked:
+        for f in RECOMPUTED:
+            a_(f"  const int cdf{f} = nbr[{f} * Ks + el];")
+            a_(f"  const bool nd{f} = cdf{f} >= 0 && (cdf{f} >> 8) != tile;")
+            a_(f"  const bool any{f} = __any(nd{f});")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for (f, k, rows) in pl["trace"][w]:
             a_(f"    // face {f}, tangent {k}, face modes {rows[0]}..{rows[-1]}")
-            _trace_job(a_, t, g, f, k, rows, "    ")
+            if masked and f in RECOMPUTED:
+                a_(f"    if (any{f})")
+                _trace_job(a_, t, g, f, k, rows, "    ",
+                           sink=lambda a_, ms, ind, f=f, k=k: _trace_stores(a_, t, f, k, ms, ind, pred=f"nd{f}"))
+            else:
+                _trace_job(a_, t, g, f, k, rows, "    ")
         a_("  }")
+
+
+def _own_trace_stage(a_, t, g, pl, nw):
+    """Stage T: the element's own traces of U on every face into LDS at
+    ((f 2 + k) NF + m) 64 + lane -- the recomputed faces from the staged field (held in
+    registers across the barrier that frees the area), the others read from the tile's
+    block of Tin (one coalesced 16-byte load per lane and quad)."""
+    NF = t.NF
+    FS, ES = trace_strides(NF)
+    NFP, FQ = FS // 2, FS // 4
+    slots = [[(f, k, m) for (f, k, rows) in pl["own"][w] for m in rows] for w in range(nw)]
+    M = max((len(x) for x in slots), default=0)
+    if M:
+        a_("  R " + ", ".join(f"ot{i}" for i in range(M)) + ";")
+    for w in range(nw):
+        if not slots[w]:
+            continue
+        pos = {x: i for i, x in enumerate(slots[w])}
+        a_(f"  if (wave == {w}) {{")
+        for (f, k, rows) in pl["own"][w]:
+            def sink(a_, ms, ind, f=f, k=k, pos=pos):
+                for m in ms:
+                    a_(ind + f"  ot{pos[(f, k, m)]} = ts_{m};")
+            a_(f"    // own trace: face {f}, tangent {k}, face modes {rows[0]}..{rows[-1]}")
+            _trace_job(a_, t, g, f, k, rows, "    ", sink=sink)
+        a_("  }")
+    a_("  __syncthreads();")
+    for w in range(nw):
+        if not slots[w]:
+            continue
+        a_(f"  if (wave == {w}) {{")
+        for i, (f, k, m) in enumerate(slots[w]):
+            a_(f"    wl[{((f * 2 + k) * NF + m) * LANES} + lane] = ot{i};")
+        a_("  }")
+    # own traces of the read faces: chunk-parallel over the waves
+    chunks = [f * FQ + j for f in READ for j in range(FQ)]
+    cnt = -(-len(chunks) // nw)
+    a_("  {")
+    a_(f"    const R* __restrict__ tin = Tin + (size_t)tile * {LANES * ES} + (size_t)lane * 4;")
+    a_("    static constexpr short kChunks[" + str(len(chunks)) + "] = {" + ", ".join(map(str, chunks)) + "};")
+    for r0 in range(0, cnt, JUMP_BATCH):
+        idx = range(r0, min(cnt, r0 + JUMP_BATCH))
+        a_("    {")
+        for i in idx:
+            ci = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {len(chunks) - 1})"
+            a_(f"      const int q{i} = kChunks[{ci}], f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
+            a_(f"      const R* so{i} = (const R*)__builtin_assume_aligned(tin + (size_t)q{i} * {LANES * 4}, 16);")
+            a_(f"      const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
+        for i in idx:
+            a_(f"      {{ const int k = c{i} >= {NFP}, m = c{i} - k * {NFP};")
+            a_(f"        const int d = ((f{i} * 2 + k) * {NF} + m) * {LANES} + lane;")
+            for jj in range(4):
+                st = f"wl[d + {jj * LANES}] = o{i}_{jj};"
+                a_(f"        {st}" if (jj == 0 and NF % 4 == 0) else f"        if (m + {jj} < {NF}) {st}")
+            a_("      }")
+        a_("    }")
+    a_("  }")
 
 
 def _phase_body(a_, t, g, Lp, pl, nw):
@@ -839,8 +933,11 @@ def _phase_body(a_, t, g, Lp, pl, nw):
             a_(f"    // volume modes {', '.join(map(str, rows))}")
             _curl_job(a_, t, rows, "    ")
         a_("  }")
+    a_("  // T: own traces of U on every face into LDS (recomputed faces from the staged")
+    a_("  // field, the others from Tin)")
+    _own_trace_stage(a_, t, g, pl, nw)
     a_("  __syncthreads();")
-    a_("  // C: jumps of the traces of U (own and neighbour chunks of its trace buffer)")
+    a_("  // C: jumps of the traces of U (neighbour from LDS in the tile, else from Tin)")
     a_("  {")
     for l in _jump_lines(t, nw):
         a_("    " + l)
@@ -951,7 +1048,7 @@ def emit_trace(p: int) -> str:
     _elem_prologue(a_)
     _stage_field(a_, t, nw, "U", "MU")
     a_("  __syncthreads();")
-    _trace_stage(a_, t, g, pl, nw)
+    _trace_stage(a_, t, g, pl, nw, masked=False)
     a_("}")
     return "\n".join(L) + "\n"
 
