@@ -112,7 +112,10 @@ FACTORED = (0, 3)  # faces whose trace goes through the collapsed tensor-product
 # where the neighbour is in another tile.  The other faces' traces are written for every
 # element and read back as the element's own traces; in-tile neighbours are read from LDS.
 RECOMPUTED = (1, 2)
-READ = (0, 3)
+
+
+def read_faces(recomputed):
+    return tuple(f for f in range(4) if f not in recomputed)
 
 
 def _blocks(t):
@@ -324,6 +327,8 @@ def _plan_traces(t, g, nw, faces=(0, 1, 2, 3), init=None):
     NF = t.NF
     NQ = (NF + 3) // 4
     units = [(f, k) for f in faces for k in range(2)]
+    if not units:
+        return [[] for _ in range(nw)], list(init) if init else [0] * nw
     rows_of = lambda i, j: list(range(4 * i, min(NF, 4 * j)))
     cap = 2 * TRACE_ROWS
     memo = {}
@@ -371,6 +376,52 @@ def _plan_traces(t, g, nw, faces=(0, 1, 2, 3), init=None):
     return [sorted(a) for a in assign], load
 
 
+def _rebalance_intervals(t, g, Lp, bins, nw, cap, rounds=400):
+    """The curl (with the own-trace jobs) and the lift run in different barrier
+    intervals, so what counts is each interval's most loaded wave.  Starting from the
+    total-cost partition, move single (m, k) blocks between waves while that lowers
+    max(curl + own traces) + max(lift + update)."""
+    rows_of = lambda bl: sorted(r for b in bl for r in b)
+    memo = {}
+
+    def parts(bl):
+        key = tuple(sorted(bl))
+        if key not in memo:
+            rows = rows_of(bl)
+            cu = _curl_cost(t, rows) if rows else 0
+            memo[key] = (cu, (_out_job_cost(t, Lp, rows) - cu) if rows else 0)
+        return memo[key]
+
+    def objective(bs):
+        cs = [parts(b) for b in bs]
+        _, own = _plan_traces(t, g, nw, RECOMPUTED, init=[c[0] for c in cs])
+        return max(own) + max(c[1] for c in cs)
+
+    bins = [list(b) for b in bins]
+    best = objective(bins)
+    for _ in range(rounds):
+        improved = False
+        for a in range(nw):
+            for blk in list(bins[a]):
+                for b in range(nw):
+                    if b == a or len(rows_of(bins[b] + [blk])) > cap:
+                        continue
+                    cand = [list(x) for x in bins]
+                    cand[a].remove(blk)
+                    cand[b].append(blk)
+                    v = objective(cand)
+                    if v < best:
+                        best, bins, improved = v, cand, True
+                        break
+                if improved:
+                    break
+            if improved:
+                break
+        if not improved:
+            break
+    return bins
+
+
 def _plan_c2(t, nw):
     """Stage C2 tasks (degree n, scalar s): face 0's jumps of degree n converted in
     place from psi to the collapsed basis (C^T), spread over the waves by cost."""
@@ -397,6 +448,8 @@ def plan(p: int, nw: int):
     ob, out_load = _balance(blks, lambda b: _out_job_cost(t, Lp, list(b)),
                             lambda bl: _out_job_cost(t, Lp, rows_of(bl)), nw,
                             lambda bl: len(rows_of(bl)) <= cap)
+    ob = _rebalance_intervals(t, g, Lp, ob, nw, cap)
+    out_load = [_out_job_cost(t, Lp, rows_of(bl)) for bl in ob]
     out_w = [[rows_of(bl)] if bl else [] for bl in ob]
     # the own-trace jobs share a barrier interval with the curl: balance them together
     curl = [sum(_curl_cost(t, rows) for rows in w) for w in out_w]
@@ -763,49 +816,64 @@ def _stage_field(a_, t, nw, X, mp):
 JUMP_BATCH = 4    # trace chunks per lane loaded before their LDS stores
 
 
-def _jump_lines(t, nw):
-    """Jumps of the tangential traces of U (own traces already in LDS, stage T):
-    neighbour minus own on interior faces, (wall - 1) times own on walls.  A neighbour
-    in the same tile is read from LDS, one in another tile from Tin (one 16-byte load
-    of its face block).  Work item (k, j): tangent k, face modes 4j..4j+3 of all four
-    faces; every read of an item's own and neighbour values (same tangent and modes,
-    any face) is made by the wave that then overwrites them with the jumps, so the
-    jumps replace the own traces in place without a barrier.  Wave w takes items w,
-    w + nw, ...; items past the end are skipped (a duplicate would race with the
-    in-place update)."""
+def _jump_items(t, nw):
+    NFP = trace_strides(t.NF)[0] // 2
+    items = [(k, jq) for k in range(2) for jq in range(NFP // 4)]
+    return items, -(-len(items) // nw)
+
+
+def _jump_prefetch(t, nw):
+    """Declarations of the jump stage at kernel scope: per face the neighbour code and
+    whether the neighbour is in the tile, and the 16-byte chunks of the off-tile
+    neighbours for this wave's items (loaded here, used after the next barrier)."""
     NF = t.NF
     FS, ES = trace_strides(NF)
     NFP, FQ = FS // 2, FS // 4
-    items = [(k, jq) for k in range(2) for jq in range(NFP // 4)]
-    cnt = -(-len(items) // nw)
-    L = ["const R cw = wall - R(1);",
-         "const int code0 = nbr[el], code1 = nbr[Ks + el], code2 = nbr[2 * Ks + el], code3 = nbr[3 * Ks + el];"]
+    items, cnt = _jump_items(t, nw)
+    L = ["const int code0 = nbr[el], code1 = nbr[Ks + el], code2 = nbr[2 * Ks + el], code3 = nbr[3 * Ks + el];"]
     for f in range(4):
         L.append(f"const int nb{f} = code{f} >= 0 ? code{f} >> 2 : el, gf{f} = code{f} >= 0 ? code{f} & 3 : {f};")
         L.append(f"const bool in{f} = code{f} >= 0 && (nb{f} >> 6) == tile, off{f} = code{f} >= 0 && !in{f};")
     for i in range(cnt):
-        L.append(f"if (wave + {i * nw} < {len(items)}) {{" if (i + 1) * nw > len(items) else "{")
-        L.append(f"  const int it = wave + {i * nw}, k = it / {NFP // 4}, c = 4 * (it - k * {NFP // 4});")
-        # off-tile neighbour chunks first (one round trip for the four faces)
+        L.append(f"R " + ", ".join(f"t{i}_{f}_{jj} = R(0)" for f in range(4) for jj in range(4)) + ";")
+        guard = f"wave + {i * nw} < {len(items)}"
+        L.append(f"{{ const int it = min(wave + {i * nw}, {len(items) - 1}), k = it / {NFP // 4}, c = 4 * (it - k * {NFP // 4});")
         for f in range(4):
-            L.append(f"  R t{f}_0 = R(0), t{f}_1 = R(0), t{f}_2 = R(0), t{f}_3 = R(0);")
-            L.append(f"  if (off{f}) {{")
+            L.append(f"  if (off{f} && {guard}) {{")
             L.append(f"    const R* sn = (const R*)__builtin_assume_aligned(Tin + (size_t)(nb{f} >> 6) * {LANES * ES} "
                      f"+ ((size_t)(gf{f} * {FQ} + (k * {NFP} + c) / 4) * {LANES} + (nb{f} & 63)) * 4, 16);")
-            L.append(f"    t{f}_0 = sn[0]; t{f}_1 = sn[1]; t{f}_2 = sn[2]; t{f}_3 = sn[3];")
+            L.append("    " + " ".join(f"t{i}_{f}_{jj} = sn[{jj}];" for jj in range(4)))
             L.append("  }")
+        L.append("}")
+    return L
+
+
+def _jump_lines(t, nw):
+    """Jumps of the tangential traces of U (own traces already in LDS, stage T):
+    neighbour minus own on interior faces, (wall - 1) times own on walls.  A neighbour
+    in the same tile is read from LDS, one in another tile was loaded from Tin (one
+    16-byte load of its face block) before the barrier (_jump_prefetch).  Work item
+    (k, j): tangent k, face modes 4j..4j+3 of all four faces; every read of an item's
+    own and neighbour values (same tangent and modes, any face) is made by the wave
+    that then overwrites them with the jumps, so the jumps replace the own traces in
+    place without a barrier.  Wave w takes items w, w + nw, ...; items past the end
+    are skipped (a duplicate would race with the in-place update)."""
+    NF = t.NF
+    NFP = trace_strides(NF)[0] // 2
+    items, cnt = _jump_items(t, nw)
+    L = ["const R cw = wall - R(1);"]
+    for i in range(cnt):
+        L.append(f"if (wave + {i * nw} < {len(items)}) {{" if (i + 1) * nw > len(items) else "{")
+        L.append(f"  const int it = wave + {i * nw}, k = it / {NFP // 4}, c = 4 * (it - k * {NFP // 4});")
         for jj in range(4):
-            if NF % 4:
-                L.append(f"  if (c + {jj} < {NF}) {{")
-            else:
-                L.append("  {")
+            L.append(f"  if (c + {jj} < {NF}) {{" if NF % 4 else "  {")
             L.append(f"    const int m = c + {jj};")
             for f in range(4):
                 L.append(f"    const R ow{f} = wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane];")
                 L.append(f"    const R nv{f} = wl[(((gf{f} * 2 + k) * {NF}) + m) * {LANES} + (nb{f} & 63)];")
             for f in range(4):
                 L.append(f"    wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane] = "
-                         f"code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{f}_{jj}) - ow{f};")
+                         f"code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{i}_{f}_{jj}) - ow{f};")
             L.append("  }")
         L.append("}")
     return L
@@ -887,29 +955,27 @@ def _own_trace_stage(a_, t, g, pl, nw):
         for i, (f, k, m) in enumerate(slots[w]):
             a_(f"    wl[{((f * 2 + k) * NF + m) * LANES} + lane] = ot{i};")
         a_("  }")
-    # own traces of the read faces: chunk-parallel over the waves
-    chunks = [f * FQ + j for f in READ for j in range(FQ)]
-    cnt = -(-len(chunks) // nw)
-    a_("  {")
-    a_(f"    const R* __restrict__ tin = Tin + (size_t)tile * {LANES * ES} + (size_t)lane * 4;")
-    a_("    static constexpr short kChunks[" + str(len(chunks)) + "] = {" + ", ".join(map(str, chunks)) + "};")
-    for r0 in range(0, cnt, JUMP_BATCH):
-        idx = range(r0, min(cnt, r0 + JUMP_BATCH))
-        a_("    {")
-        for i in idx:
-            ci = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {len(chunks) - 1})"
-            a_(f"      const int q{i} = kChunks[{ci}], f{i} = q{i} / {FQ}, c{i} = 4 * (q{i} - f{i} * {FQ});")
-            a_(f"      const R* so{i} = (const R*)__builtin_assume_aligned(tin + (size_t)q{i} * {LANES * 4}, 16);")
-            a_(f"      const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
-        for i in idx:
-            a_(f"      {{ const int k = c{i} >= {NFP}, m = c{i} - k * {NFP};")
-            a_(f"        const int d = ((f{i} * 2 + k) * {NF} + m) * {LANES} + lane;")
-            for jj in range(4):
-                st = f"wl[d + {jj * LANES}] = o{i}_{jj};"
-                a_(f"        {st}" if (jj == 0 and NF % 4 == 0) else f"        if (m + {jj} < {NF}) {st}")
-            a_("      }")
-        a_("    }")
-    a_("  }")
+    # own traces of the read faces: chunk-parallel over the waves, loads issued first
+    chunks = [f * FQ + j for f in read_faces(RECOMPUTED) for j in range(FQ)]
+    cnt = -(-len(chunks) // nw) if chunks else 0
+    if cnt:
+        a_(f"  const R* __restrict__ tin = Tin + (size_t)tile * {LANES * ES} + (size_t)lane * 4;")
+        a_("  static constexpr short kChunks[" + str(len(chunks)) + "] = {" + ", ".join(map(str, chunks)) + "};")
+    for i in range(cnt):
+        ci = f"wave + {i * nw}" if i < cnt - 1 else f"min(wave + {i * nw}, {len(chunks) - 1})"
+        a_(f"  const int oq{i} = kChunks[{ci}];")
+        a_(f"  const R* so{i} = (const R*)__builtin_assume_aligned(tin + (size_t)oq{i} * {LANES * 4}, 16);")
+        a_(f"  const R o{i}_0 = so{i}[0], o{i}_1 = so{i}[1], o{i}_2 = so{i}[2], o{i}_3 = so{i}[3];")
+    a_("  // the jump stage's off-tile neighbour chunks, in flight across the next barrier")
+    for l in _jump_prefetch(t, nw):
+        a_("  " + l)
+    for i in range(cnt):
+        a_(f"  {{ const int f = oq{i} / {FQ}, c = 4 * (oq{i} - f * {FQ}), k = c >= {NFP}, m = c - k * {NFP};")
+        a_(f"    const int d = ((f * 2 + k) * {NF} + m) * {LANES} + lane;")
+        for jj in range(4):
+            st = f"wl[d + {jj * LANES}] = o{i}_{jj};"
+            a_(f"    {st}" if (jj == 0 and NF % 4 == 0) else f"    if (m + {jj} < {NF}) {st}")
+        a_("  }")
 
 
 def _phase_body(a_, t, g, Lp, pl, nw):
