@@ -13,12 +13,18 @@ Contents
   dg      -- mesh geometry, L2 projection, strong-form H / weak-form E central-flux
              right-hand sides, symplectic Euler (Section 3), energies, power
              iteration for the time-step bound, dense operator assembly.
+  stab    -- the stabilised central flux with face unknowns H^F (Section 2.1):
+             per-face tangential unknowns, their update from the tangential
+             jump of E, the extra E-equation term, energies, assembly.
 
 Pins (tests/test_oracle.py) tie each function to something other than
 itself: closed-form norms, orthogonality, integration by parts, exact
 polynomial reproduction of curl, skew-symmetry of the semi-discrete system,
 exact conservation of the leapfrog invariant, the scalar stability
-threshold, and h-convergence to the exact PEC cube eigenmodes.
+threshold, and h-convergence to the exact PEC cube eigenmodes
+(tests/test_oracle_stab.py for the stabilised flux: skew-symmetry, the
+null-space dimension in closed form, cavity eigenvalues kept and spurious
+ones removed, reduction to the central flux, exact leapfrog invariant).
 
 Parity unpinned: the paper's own experiments (the spherical resonator of
 Section 2.2 and the timings of Section 3.5) cannot be reproduced here: the
@@ -26,4 +32,5 @@ meshes and the reference data are not available.
 """
 from .basis import eval_basis, mode_list, num_modes, tet_quadrature, triangle_quadrature  # noqa: F401
 from .dg import Mesh, Solver, build_mesh  # noqa: F401
+from .stab import StabilizedSolver  # noqa: F401
 from .jacobi import djacobi, gauss_jacobi, jacobi  # noqa: F401
