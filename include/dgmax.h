@@ -174,6 +174,51 @@ int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const vo
 int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
                     hipStream_t stream);
 
+/* Stabilised central flux with face unknowns H^F (Section 2.1), the paper's
+ * recommended method: it keeps the discrete energy and removes the spurious
+ * modes of the central flux.  Besides E and H the state holds, on every face, a
+ * tangential field H^F of degree p with
+ *     (h_F/alpha) (dH^F/dt, h^F)_F = ([E] x nu, h^F)_F,
+ *     (eps dE/dt, e)_T gains (H^F x nu_T, e)_F on each face of T (twice on walls),
+ * [E] = E_s - E_nb across the face (2 E on walls, ghost E_nb = -E), alpha =
+ * alpha0 p^2, h_F = 3 min |T| / |F| over the face's elements (the smaller height
+ * over F).  The paper prints alpha/h as the face mass; its definition
+ * H^F = alpha [E] x nu / (i omega h) and its penalty S ~ alpha/h both give the
+ * mass h/alpha used here.  The central entry points above are unaffected.
+ *
+ * dgm_set_stab_alpha sets alpha0 (> 0; DGM_ERR_ARG otherwise); the stabilised
+ * calls below return DGM_ERR_STATE until it is called, and rebuild their face data
+ * (host FP64, one upload) after an order change.
+ *
+ * HF: caller-owned device buffer of dgm_num_face_unknowns() = 8 NF K values of the
+ * dtype (NF = dgm_num_face_modes(p)), entry ((k NF + m) 4 + f) K + e = the
+ * coefficient of face mode m (the orthonormal triangle basis of the face
+ * parametrised by its vertices in ascending global id, modes ordered by degree)
+ * of H^F . t_k on local face f of element e, where t_1, t_2 are the face's edge
+ * vectors from its lowest-id vertex (both sides of a face agree on them).  A face
+ * is held by one side: the element with the smaller index (the element itself on
+ * a wall); the other side's entries are neither read nor written. */
+int dgm_set_stab_alpha(dgm_mesh* mesh, double alpha0);
+int dgm_num_face_unknowns(const dgm_mesh* mesh, int64_t* n);
+/* Rates: dH = M_mu^{-1} C E (as dgm_apply_curl) and dHF = dH^F/dt from E (held
+ * entries only; the others are set to 0), dE from H and HF.  Any output may be NULL;
+ * outputs must not alias inputs. */
+int dgm_apply_stab(dgm_mesh* mesh, int dtype, const void* E, const void* H, const void* HF, void* dE, void* dH,
+                   void* dHF, hipStream_t stream);
+/* nsteps symplectic-Euler steps in place: H and H^F from E, then E from H and H^F
+ * (Section 3); honours dgm_set_check_interval as dgm_step does. */
+int dgm_step_stab(dgm_mesh* mesh, int dtype, void* E, void* H, void* HF, double dt, int64_t nsteps,
+                  hipStream_t stream);
+/* out[0] = W + 1/2 sum_F (h_F/alpha) (H^F, H^F)_F, out[1] = Q with the face term
+ * 1/2 sum_F (h_F/alpha) (H^F, H^F_next)_F, the quantity the stabilised step
+ * conserves exactly; H_next and H^F_next are formed internally (dt = 0: Q = W). */
+int dgm_energy_stab(dgm_mesh* mesh, int dtype, const void* E, const void* H, const void* HF, double dt,
+                    double out[2], hipStream_t stream);
+/* dgm_estimate_dt for the stabilised operator: power iteration on
+ * E -> -dE(dH(E), dHF(E)) (the face term raises the spectral radius). */
+int dgm_estimate_dt_stab(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
+                         hipStream_t stream);
+
 /* Dense reference-operator variant on the matrix cores.  The same semi-discrete
  * operator as dgm_apply_curl / dgm_step, applied as the dense O(N^2) element
  * matrices that Section 3.2 avoids (curl in the derivative frame, four trace

@@ -175,6 +175,38 @@ __global__ void __launch_bounds__(kRedThreads) dot_partial_kernel(const R* __res
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Partial sums (FP64) of the face-unknown energy product sum over owner sides and face
+// modes of a_m^T W b_m, with a, b the face unknowns (layout ((k NF + m) 4 + f) K + e)
+// and W the side's symmetric 2x2 weight (12,K): (h_F/alpha) 2|F| G^{-1}, zero on
+// sides that do not own their face.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) fdot_partial_kernel(const R* __restrict__ A, const R* __restrict__ B,
+                                                                   const double* __restrict__ W, int NF, int K,
+                                                                   double* __restrict__ partial) {
+  __shared__ double red[kRedThreads];
+  const int e = blockIdx.x * kRedThreads + threadIdx.x;
+  double acc = 0.0;
+  if (e < K) {
+    const size_t Ks = (size_t)K;
+    for (int f = 0; f < 4; ++f) {
+      const double w00 = W[(3 * f + 0) * Ks + e], w01 = W[(3 * f + 1) * Ks + e], w11 = W[(3 * f + 2) * Ks + e];
+      if (w00 == 0.0 && w01 == 0.0 && w11 == 0.0) continue;
+      for (int m = 0; m < NF; ++m) {
+        const size_t i0 = ((size_t)(m * 4 + f)) * Ks + e, i1 = ((size_t)((NF + m) * 4 + f)) * Ks + e;
+        const double a0 = A[i0], a1 = A[i1], b0 = B[i0], b1 = B[i1];
+        acc += w00 * a0 * b0 + w01 * (a0 * b1 + a1 * b0) + w11 * a1 * b1;
+      }
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014) mapped to [-1, 1): start vector of the
 // power iteration, identical to the host reference generator.
 template <typename R>
@@ -222,6 +254,15 @@ struct dgm_mesh {
   int partial_n = 0;
   double* d_res = nullptr;  // four FP64 reduction results (energies)
   int64_t check_every = 0;  // dgm_step: steps between finiteness checks (0: none)
+  // stabilised flux (Section 2.1): alpha = stab_alpha0 p^2 once dgm_set_stab_alpha was
+  // called; per owner side of every face the FP32/FP64 2x2 update matrices (16,K) and
+  // the FP64 energy weights (12,K), built for order stab_p in one device block
+  double stab_alpha0 = 0.0;
+  int stab_p = 0;
+  void* d_stab = nullptr;
+  float* d_SC32 = nullptr;
+  double* d_SC64 = nullptr;
+  double* d_WF = nullptr;
   // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
   DenseOps* dense[2] = {nullptr, nullptr};
   float* d_jump = nullptr;
@@ -437,7 +478,17 @@ int run_trace(dgm_mesh* m, const R* U, int fld, R* T, hipStream_t s) {
 // One phase on stored-frame data.  fld_u: 0 if U is E (H update), 1 if U is H.
 // Tin holds the traces of U; Tout (or nullptr) receives those of the updated V.
 template <typename R>
-int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin, R* Tout, hipStream_t s) {
+const R* SCdev(const dgm_mesh* m);
+template <>
+const float* SCdev<float>(const dgm_mesh* m) { return m->d_SC32; }
+template <>
+const double* SCdev<double>(const dgm_mesh* m) { return m->d_SC64; }
+
+// With HF (stabilised flux): the H phase (fld_u 0) advances the face unknowns by fdt
+// times their rate; the E phase reads them.
+template <typename R>
+int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin, R* Tout, hipStream_t s,
+              R* HF = nullptr, double fdt = 0.0) {
   PhaseArgs<R> a;
   a.U = U;
   a.V = V;
@@ -452,6 +503,9 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
   a.blocks = (int)((m->K + 63) / 64);
   a.streaming = step_bytes(m->K, m->p, sizeof(R)) > kStreamingBytes;
   a.stream = s;
+  a.HF = HF;
+  a.SC = HF ? SCdev<R>(m) : nullptr;
+  a.fdt = (R)fdt;
   HIP_TRY(phase(a, m->p));
   return DGM_OK;
 }
@@ -459,7 +513,7 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
 // Covariant rate: out = d/dt of the other field from the covariant input `in`.
 // fld_u = 0: in = E, out = dH;  fld_u = 1: in = H, out = dE.
 template <typename R>
-int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s) {
+int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF = nullptr, double fdt = 0.0) {
   const size_t n = (size_t)3 * num_modes(m->p) * m->K;
   int rc;
   if ((rc = ensure_scratch(m, n * sizeof(R)))) return rc;
@@ -470,7 +524,7 @@ int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s) {
   if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
   if ((rc = run_trace<R>(m, tmp, fld_u, T[fld_u], s))) return rc;
   if ((rc = fill<R>(out, n, (R)0, s))) return rc;
-  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s))) return rc;
+  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt))) return rc;
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
 
@@ -536,7 +590,7 @@ int mesh_work(dgm_mesh* m, bool reductions, StepWork<R>* ws) {
 // ws: trace buffers (always) and, for checks or probes, the reduction buffers.
 template <typename R>
 int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s, const StepWork<R>& ws,
-              const R* w = nullptr, double* d_sig = nullptr) {
+              const R* w = nullptr, double* d_sig = nullptr, R* HF = nullptr) {
   int rc;
   if (nsteps == 0) return DGM_OK;
   const size_t n = (size_t)3 * num_modes(m->p) * m->K;
@@ -550,8 +604,8 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
   for (int64_t it = 0; it < nsteps; ++it) {
     // H update from curl E (writes the traces of H), then E update from curl H
     // (writes the traces of E for the next step, except after the last one)
-    if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s))) return rc;
-    if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s))) return rc;
+    if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s, HF, dt))) return rc;
+    if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s, HF))) return rc;
     if (w) {
       hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, (const R*)E, w, n, ws.partial);
       HIP_TRY(hipGetLastError());
@@ -683,6 +737,194 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipFreeAsync(base, s);  // freed on every path
+  const hipError_t e3 = hipStreamSynchronize(s);
+  if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
+  const double rho = -h[0] / h[1];
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
+  if (rho_out) *rho_out = rho;
+  *dt = cfl * 2.0 / std::sqrt(rho);
+  return DGM_OK;
+}
+
+// Face data of the stabilised flux for the current order: per element side that owns its
+// face (a wall side, or the side of the smaller element index) with sorted-vertex edge
+// vectors t_1, t_2 of the face, outward unit normal nu, area |F| and Gram matrix G:
+// the update matrix C = -(alpha/h_F) c, nu x t_k = sum_i c[k][i] t_i (16,K: 4 per face),
+// and the energy weight (h_F/alpha) 2|F| G^{-1} (12,K: 3 per face), with
+// h_F = 3 min |T| / |F| over the face's elements and alpha = alpha0 p^2 (FP64 on the host).
+int stab_ready(dgm_mesh* m) {
+  if (!(m->stab_alpha0 > 0.0)) return fail(DGM_ERR_STATE, "stabilised flux not set (dgm_set_stab_alpha)");
+  if (m->d_stab && m->stab_p == m->p) return DGM_OK;
+  const int64_t K = m->K;
+  const size_t Ks = (size_t)K;
+  const double alpha = m->stab_alpha0 * m->p * m->p;
+  std::vector<float> sc32(16 * Ks, 0.f);
+  std::vector<double> sc64(16 * Ks, 0.0), wf(12 * Ks, 0.0);
+  for (int64_t e = 0; e < K; ++e) {
+    double P[4][3] = {{0, 0, 0}};
+    for (int q = 1; q < 4; ++q)
+      for (int d = 0; d < 3; ++d) P[q][d] = m->F[9 * e + 3 * d + (q - 1)];
+    for (int f = 0; f < 4; ++f) {
+      const int code = m->nbr[f * Ks + e];
+      const int64_t nb = code >= 0 ? code >> 2 : -1;
+      if (code >= 0 && nb < e) continue;  // the neighbour owns this face
+      int w[3], c = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != f) w[c++] = q;
+      double t[2][3], n[3];
+      for (int d = 0; d < 3; ++d) {
+        t[0][d] = P[w[1]][d] - P[w[0]][d];
+        t[1][d] = P[w[2]][d] - P[w[0]][d];
+      }
+      n[0] = t[0][1] * t[1][2] - t[0][2] * t[1][1];
+      n[1] = t[0][2] * t[1][0] - t[0][0] * t[1][2];
+      n[2] = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+      const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      double out = 0.0;
+      for (int d = 0; d < 3; ++d) out += n[d] * (P[f][d] - P[w[0]][d]);
+      const double sgn = out > 0.0 ? -1.0 : 1.0;  // away from the opposite vertex
+      double nu[3];
+      for (int d = 0; d < 3; ++d) nu[d] = sgn * n[d] / nn;
+      const double area = 0.5 * nn;
+      double G[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) G[a][b] = t[a][0] * t[b][0] + t[a][1] * t[b][1] + t[a][2] * t[b][2];
+      const double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+      const double Gi[2][2] = {{G[1][1] / det, -G[0][1] / det}, {-G[1][0] / det, G[0][0] / det}};
+      const double Je = std::fabs(m->J[e]);
+      const double hF = (code >= 0 ? std::min(Je, std::fabs(m->J[nb])) : Je) / (2.0 * area);
+      for (int k = 0; k < 2; ++k) {
+        double v[3] = {nu[1] * t[k][2] - nu[2] * t[k][1], nu[2] * t[k][0] - nu[0] * t[k][2],
+                       nu[0] * t[k][1] - nu[1] * t[k][0]};
+        double r[2];
+        for (int i = 0; i < 2; ++i) r[i] = t[i][0] * v[0] + t[i][1] * v[1] + t[i][2] * v[2];
+        for (int i = 0; i < 2; ++i) {
+          const double cki = Gi[i][0] * r[0] + Gi[i][1] * r[1];
+          const double Cv = -(alpha / hF) * cki;
+          sc64[(4 * f + 2 * k + i) * Ks + e] = Cv;
+          sc32[(4 * f + 2 * k + i) * Ks + e] = (float)Cv;
+        }
+      }
+      const double sw = (hF / alpha) * 2.0 * area;
+      wf[(3 * f + 0) * Ks + e] = sw * Gi[0][0];
+      wf[(3 * f + 1) * Ks + e] = sw * Gi[0][1];
+      wf[(3 * f + 2) * Ks + e] = sw * Gi[1][1];
+    }
+  }
+  const size_t b32 = (16 * Ks * sizeof(float) + 255) & ~size_t(255);
+  const size_t b64 = (16 * Ks * sizeof(double) + 255) & ~size_t(255);
+  if (!m->d_stab) HIP_TRY(hipMalloc(&m->d_stab, b32 + b64 + 12 * Ks * sizeof(double)));
+  char* base = static_cast<char*>(m->d_stab);
+  m->d_SC32 = reinterpret_cast<float*>(base);
+  m->d_SC64 = reinterpret_cast<double*>(base + b32);
+  m->d_WF = reinterpret_cast<double*>(base + b32 + b64);
+  HIP_TRY(hipMemcpy(m->d_SC32, sc32.data(), sc32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->d_SC64, sc64.data(), sc64.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->d_WF, wf.data(), wf.size() * sizeof(double), hipMemcpyHostToDevice));
+  m->stab_p = m->p;
+  return DGM_OK;
+}
+
+size_t face_unknowns(const dgm_mesh* m) { return (size_t)8 * num_face_modes(m->p) * (size_t)m->K; }
+
+template <typename R>
+int fdot(dgm_mesh* m, const R* A, const R* B, double* d_out, hipStream_t s) {
+  const int nb = (int)((m->K + kRedThreads - 1) / kRedThreads);
+  int rc;
+  if ((rc = ensure_partial(m, nb))) return rc;
+  hipLaunchKernelGGL(fdot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, A, B, m->d_WF,
+                     num_face_modes(m->p), (int)m->K, m->d_partial);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_out);
+  HIP_TRY(hipGetLastError());
+  return DGM_OK;
+}
+
+// dH and dHF from E (either may be null), dE from H and HF.
+template <typename R>
+int apply_stab_impl(dgm_mesh* m, const R* E, const R* H, const R* HF, R* dE, R* dH, R* dHF, hipStream_t s) {
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  int rc;
+  if (dH || dHF) {
+    R* outH = dH;
+    if (!outH) {
+      if ((rc = ensure_scratch(m, 2 * n * sizeof(R)))) return rc;
+      outH = static_cast<R*>(m->d_scratch) + n;  // the rate's copy of E uses the first half
+    }
+    if (dHF && (rc = fill<R>(dHF, face_unknowns(m), (R)0, s))) return rc;
+    if ((rc = rate_impl<R>(m, E, outH, 0, s, dHF, 1.0))) return rc;
+  }
+  if (dE && (rc = rate_impl<R>(m, H, dE, 1, s, const_cast<R*>(HF), 0.0))) return rc;
+  return DGM_OK;
+}
+
+// W and Q with the face term: central parts from energy_impl, then
+// 1/2 (HF, W HF) and 1/2 (HF, W HF_next) with HF_next = HF + dt dHF(E).
+template <typename R>
+int energy_stab_impl(dgm_mesh* m, const R* E, const R* H, const R* HF, double dt, double out[2], hipStream_t s) {
+  int rc;
+  if ((rc = energy_impl<R>(m, E, H, dt == 0.0 ? H : nullptr, dt, out, s))) return rc;
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K, nh = face_unknowns(m);
+  R* hn = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&hn), nh * sizeof(R), s));
+  rc = DGM_OK;
+  if (dt != 0.0) {
+    if ((rc = ensure_scratch(m, 2 * n * sizeof(R))) == DGM_OK) {
+      if (hipMemcpyAsync(hn, HF, nh * sizeof(R), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = fail(DGM_ERR_HIP, "face unknown copy failed");
+      if (!rc) rc = rate_impl<R>(m, E, static_cast<R*>(m->d_scratch) + n, 0, s, hn, dt);
+    }
+  }
+  if (!rc) rc = fdot<R>(m, HF, HF, m->d_res + 0, s);
+  if (!rc) rc = fdot<R>(m, HF, dt != 0.0 ? hn : HF, m->d_res + 1, s);
+  double h[2] = {0, 0};
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(h, m->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(hn, s);
+  const hipError_t e3 = hipStreamSynchronize(s);
+  if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
+  out[0] += 0.5 * h[0];
+  out[1] += 0.5 * h[1];
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(DGM_ERR_UNSTABLE, "non-finite energy");
+  return DGM_OK;
+}
+
+// Power iteration on E -> -dE(dH(E), dHF(E)) (the stabilised second-order operator),
+// Rayleigh quotient in the M_eps inner product.
+template <typename R>
+int estimate_stab_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
+  int rc = DGM_OK;
+  const size_t n = (size_t)3 * num_modes(m->p) * m->K, nh = face_unknowns(m);
+  R* x = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), (3 * n + nh) * sizeof(R) + 5 * sizeof(double), s));
+  R* const base = x;
+  R* y = x + n;
+  R* z = y + n;
+  R* yf = z + n;
+  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(yf + nh) + 7) & ~uintptr_t(7));
+  const unsigned blocks = flat_blocks(n);
+  hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, x, n, (unsigned long long)seed);
+  if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "start vector kernel launch failed");
+  for (int it = 0; it < iters && !rc; ++it) {
+    if ((rc = apply_stab_impl<R>(m, x, nullptr, nullptr, nullptr, y, yf, s))) break;
+    if ((rc = apply_stab_impl<R>(m, nullptr, y, yf, z, nullptr, nullptr, s))) break;
+    if ((rc = mdot<R>(m, x, z, 0, d + 0, s))) break;
+    if ((rc = mdot<R>(m, x, x, 0, d + 1, s))) break;
+    if ((rc = mdot<R>(m, z, z, 0, d + 2, s))) break;
+    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, z, n, d + 2);
+    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
+    std::swap(x, z);
+  }
+  double h[3] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(base, s);
   const hipError_t e3 = hipStreamSynchronize(s);
   if (rc) return rc;
   HIP_TRY(e);
@@ -864,6 +1106,7 @@ int dgm_destroy(dgm_mesh* m) {
   dense_free(m->dense[0]);
   dense_free(m->dense[1]);
   hipFree(m->d_jump);
+  hipFree(m->d_stab);
   delete m;
   return DGM_OK;
 }
@@ -956,6 +1199,75 @@ int dgm_step_probe(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t 
   HIP_TRY(e2);
   HIP_TRY(e3);
   return DGM_OK;
+}
+
+int dgm_set_stab_alpha(dgm_mesh* m, double alpha0) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  if (!(alpha0 > 0.0) || !std::isfinite(alpha0)) return fail(DGM_ERR_ARG, "alpha0 must be positive and finite");
+  m->stab_alpha0 = alpha0;
+  m->stab_p = 0;  // face data rebuilt on the next stabilised call
+  return DGM_OK;
+}
+
+int dgm_num_face_unknowns(const dgm_mesh* m, int64_t* n) {
+  if (!m || !n) return fail(DGM_ERR_ARG, "null argument");
+  if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
+  *n = (int64_t)face_unknowns(m);
+  return DGM_OK;
+}
+
+int dgm_apply_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const void* HF, void* dE, void* dH, void* dHF,
+                   hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if ((rc = stab_ready(m))) return rc;
+  if (((dH || dHF) && !E) || (dE && (!H || !HF))) return fail(DGM_ERR_ARG, "output requested without its input");
+  const void* outs[3] = {dE, dH, dHF};
+  for (const void* o : outs)
+    if (o && (o == E || o == H || o == HF)) return fail(DGM_ERR_ARG, "outputs alias inputs");
+  if (dtype == DGM_F32)
+    return apply_stab_impl<float>(m, (const float*)E, (const float*)H, (const float*)HF, (float*)dE, (float*)dH,
+                                  (float*)dHF, s);
+  return apply_stab_impl<double>(m, (const double*)E, (const double*)H, (const double*)HF, (double*)dE, (double*)dH,
+                                 (double*)dHF, s);
+}
+
+int dgm_step_stab(dgm_mesh* m, int dtype, void* E, void* H, void* HF, double dt, int64_t nsteps, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if ((rc = stab_ready(m))) return rc;
+  if (!E || !H || !HF || E == H || E == HF || H == HF || nsteps < 0 || !std::isfinite(dt))
+    return fail(DGM_ERR_ARG, "bad step arguments");
+  if (nsteps == 0) return DGM_OK;
+  const bool red = m->check_every > 0;
+  if (dtype == DGM_F32) {
+    StepWork<float> ws;
+    if ((rc = mesh_work<float>(m, red, &ws))) return rc;
+    return step_impl<float>(m, (float*)E, (float*)H, dt, nsteps, s, ws, nullptr, nullptr, (float*)HF);
+  }
+  StepWork<double> ws;
+  if ((rc = mesh_work<double>(m, red, &ws))) return rc;
+  return step_impl<double>(m, (double*)E, (double*)H, dt, nsteps, s, ws, nullptr, nullptr, (double*)HF);
+}
+
+int dgm_energy_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const void* HF, double dt, double out[2],
+                    hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if ((rc = stab_ready(m))) return rc;
+  if (!E || !H || !HF || !out || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad energy arguments");
+  return dtype == DGM_F32 ? energy_stab_impl<float>(m, (const float*)E, (const float*)H, (const float*)HF, dt, out, s)
+                          : energy_stab_impl<double>(m, (const double*)E, (const double*)H, (const double*)HF, dt, out, s);
+}
+
+int dgm_estimate_dt_stab(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
+                         hipStream_t s) {
+  int rc = check_order(m, DGM_F32);
+  if (rc) return rc;
+  if ((rc = stab_ready(m))) return rc;
+  if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
+  return m->p <= DGM_MAX_ORDER_F64 ? estimate_stab_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
+                                   : estimate_stab_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
 }
 
 }  // extern "C"

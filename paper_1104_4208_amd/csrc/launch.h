@@ -70,6 +70,12 @@ struct PhaseArgs {
   int blocks;       // ceil(K / 64)
   int streaming;    // nonzero: nontemporal field and trace-store accesses (ldf, stf, store4s)
   hipStream_t stream;
+  // stabilised flux (nullptr HF: central flux).  HF: face unknowns sigma, layout
+  // ((k NF + m) 4 + f) K + e, held by each face's owner side; SC: (16,K) the owner's 2x2
+  // update matrices; fdt: the step of sigma in the H phase (sigma += fdt C dtau)
+  R* HF = nullptr;
+  const R* SC = nullptr;
+  R fdt = R(0);
 };
 
 template <typename R>

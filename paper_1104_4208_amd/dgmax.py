@@ -50,6 +50,12 @@ SIGNATURES = {
     "dgm_energy": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
     "dgm_step_probe": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p, _pd, _c_p]),
     "dgm_estimate_dt": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
+    "dgm_set_stab_alpha": (_c_i, [_c_p, _c_d]),
+    "dgm_num_face_unknowns": (_c_i, [_c_p, _pi64]),
+    "dgm_apply_stab": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "dgm_step_stab": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _c_i64, _c_p]),
+    "dgm_energy_stab": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_d, _pd, _c_p]),
+    "dgm_estimate_dt_stab": (_c_i, [_c_p, _c_d, _c_i, ctypes.c_uint64, _pd, _pd, _c_p]),
     "dgm_apply_curl_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step_dense": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
     "dgm_batch_create": (_c_i, [_c_i, ctypes.POINTER(_c_p)]),
@@ -279,6 +285,74 @@ class Mesh:
         _check(load_library().dgm_energy(self._h, code, _ptr(E), _ptr(H), _ptr(Hn), float(dt), out,
                                          _stream()))
         return out[0], out[1]
+
+    # -- stabilised central flux with face unknowns (include/dgmax.h) --------------
+    def set_stab_alpha(self, alpha0: float = 1.0):
+        """Use alpha = alpha0 p^2 in the stabilised-flux calls below."""
+        _check(load_library().dgm_set_stab_alpha(self._h, float(alpha0)))
+        return self
+
+    @property
+    def num_face_unknowns(self) -> int:
+        n = ctypes.c_int64()
+        _check(load_library().dgm_num_face_unknowns(self._h, ctypes.byref(n)))
+        return n.value
+
+    def face_zeros(self, dtype=None):
+        """A zeroed face-unknown buffer, shape (2, NF, 4, K)."""
+        torch = _torch()
+        return torch.zeros((2, num_face_modes(self.p), 4, self.K), dtype=dtype or torch.float32, device="cuda")
+
+    def _faces(self, t, name, dtype):
+        torch = _torch()
+        if t is None:
+            return None
+        shape = (2, num_face_modes(self.p), 4, self.K)
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+            raise DGMError(f"{name} must be a contiguous device tensor of shape {shape}")
+        if t.dtype != dtype:
+            raise DGMError(f"{name} has dtype {t.dtype}, expected {dtype}")
+        return t
+
+    def apply_stab(self, E=None, H=None, HF=None, want_dE=True, want_dH=True, want_dHF=True):
+        """Stabilised rates: (dE from H and HF, dH from E, dHF from E); an output is
+        computed when its inputs are given and it is wanted, else None."""
+        torch = _torch()
+        (E, H), code = self._fields(E=E, H=H)
+        dtype = (E if E is not None else H).dtype
+        HF = self._faces(HF, "HF", dtype)
+        dE = torch.empty_like(H) if (H is not None and HF is not None and want_dE) else None
+        dH = torch.empty_like(E) if (E is not None and want_dH) else None
+        dHF = torch.empty((2, num_face_modes(self.p), 4, self.K), dtype=dtype, device="cuda") \
+            if (E is not None and want_dHF) else None
+        _check(load_library().dgm_apply_stab(self._h, code, _ptr(E), _ptr(H), _ptr(HF), _ptr(dE), _ptr(dH), _ptr(dHF),
+                                             _stream()))
+        return dE, dH, dHF
+
+    def step_stab(self, E, H, HF, dt: float, nsteps: int = 1):
+        (E, H), code = self._fields(E=E, H=H)
+        HF = self._faces(HF, "HF", E.dtype)
+        if E is None or H is None or HF is None:
+            raise DGMError("step_stab needs E, H and HF")
+        _check(load_library().dgm_step_stab(self._h, code, _ptr(E), _ptr(H), _ptr(HF), float(dt), int(nsteps),
+                                            _stream()))
+        return E, H, HF
+
+    def energy_stab(self, E, H, HF, dt: float = 0.0):
+        """(W, Q) with the face-unknown term, FP64."""
+        (E, H), code = self._fields(E=E, H=H)
+        HF = self._faces(HF, "HF", E.dtype)
+        if E is None or H is None or HF is None:
+            raise DGMError("energy_stab needs E, H and HF")
+        out = (ctypes.c_double * 2)()
+        _check(load_library().dgm_energy_stab(self._h, code, _ptr(E), _ptr(H), _ptr(HF), float(dt), out, _stream()))
+        return out[0], out[1]
+
+    def estimate_dt_stab(self, cfl: float = 0.5, iters: int = 50, seed: int = 1):
+        dt, rho = ctypes.c_double(), ctypes.c_double()
+        _check(load_library().dgm_estimate_dt_stab(self._h, float(cfl), int(iters), int(seed), ctypes.byref(dt),
+                                                   ctypes.byref(rho), _stream()))
+        return dt.value, rho.value
 
     def apply_curl_dense(self, E=None, H=None, prec: int = DGM_BF16, dE=None, dH=None):
         """Dense matrix-core variant of apply_curl (FP32 fields, 16-bit operands)."""

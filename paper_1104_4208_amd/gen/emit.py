@@ -872,11 +872,54 @@ def _jump_lines(t, nw):
                 L.append(f"    const R ow{f} = wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane];")
                 L.append(f"    const R nv{f} = wl[(((gf{f} * 2 + k) * {NF}) + m) * {LANES} + (nb{f} & 63)];")
             for f in range(4):
-                L.append(f"    wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane] = "
-                         f"code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{i}_{f}_{jj}) - ow{f};")
+                L.append(f"    R jf{f} = code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{i}_{f}_{jj}) - ow{f};")
+            # stabilised flux, E phase: the face unknowns (held by the face's owner side)
+            # enter the jump of H as -2 sigma (-4 sigma on walls, whose test-function jump is 2 e)
+            L.append("    if constexpr (STAB) {")
+            L.append("      if (wall > R(0)) {")
+            L.append(f"        const size_t hb = (size_t)((k * {NF} + m) * 4) * Ks;")
+            for f in range(4):
+                L.append(f"        {{ const bool own = code{f} < 0 || el < nb{f};")
+                L.append(f"          jf{f} -= (code{f} < 0 ? R(4) : R(2)) * HF[hb + (size_t)(own ? {f} : gf{f}) * Ks + (own ? el : nb{f})]; }}")
+            L.append("      }")
+            L.append("    }")
+            for f in range(4):
+                L.append(f"    wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane] = jf{f};")
             L.append("  }")
         L.append("}")
     return L
+
+
+def _stab_stage(a_, t, nw):
+    """Stabilised flux, H phase: the face unknowns sigma (tangential components
+    H^F . t_k of every face mode, held by the face's owner side: the element with the
+    smaller index, or the element itself on a wall) advance from the jumps of E in
+    LDS, sigma += fdt * C_f (dtau_0, dtau_1) with the owner's 2x2 matrix
+    C_f = -(alpha / h_F) c_f, nu x t_k = sum_i c_f[k][i] t_i.  Layout of HF:
+    ((k NF + m) 4 + f) K + e.  Wave w takes modes w, w + nw, ...; then a barrier
+    (stage C2 overwrites face 0's jumps)."""
+    NF = t.NF
+    a_("  if constexpr (STAB) {")
+    a_("    if (wall < R(0) && act) {")
+    for f in range(4):
+        a_(f"      const bool so{f} = code{f} < 0 || el < nb{f};")
+        a_(f"      const R sc{f}_0 = SC[{4 * f + 0} * Ks + el], sc{f}_1 = SC[{4 * f + 1} * Ks + el], "
+           f"sc{f}_2 = SC[{4 * f + 2} * Ks + el], sc{f}_3 = SC[{4 * f + 3} * Ks + el];")
+    a_(f"      for (int m = wave; m < {NF}; m += {nw}) {{")
+    for f in range(4):
+        a_(f"        if (so{f}) {{")
+        a_(f"          const R d0 = wl[({2 * f} * {NF} + m) * {LANES} + lane], d1 = wl[({2 * f + 1} * {NF} + m) * {LANES} + lane];")
+        a_(f"          R* h0 = HF + ((size_t)(m * 4 + {f})) * Ks + el;")
+        a_(f"          R* h1 = HF + ((size_t)(({NF} + m) * 4 + {f})) * Ks + el;")
+        a_(f"          const R u0 = *h0 + fdt * (sc{f}_0 * d0 + sc{f}_1 * d1);")
+        a_(f"          const R u1 = *h1 + fdt * (sc{f}_2 * d0 + sc{f}_3 * d1);")
+        a_("          *h0 = u0;")
+        a_("          *h1 = u1;")
+        a_("        }")
+    a_("      }")
+    a_("    }")
+    a_("    __syncthreads();")
+    a_("  }")
 
 
 def _c2_stage(a_, t, pl, nw):
@@ -1009,6 +1052,7 @@ def _phase_body(a_, t, g, Lp, pl, nw):
         a_("    " + l)
     a_("  }")
     a_("  __syncthreads();")
+    _stab_stage(a_, t, nw)
     a_("  // C2: face 0's jumps from psi to the collapsed basis of the lift factors, in place")
     _c2_stage(a_, t, pl, nw)
     a_("  __syncthreads();")
@@ -1084,10 +1128,12 @@ def emit_phase(p: int) -> str:
     a_ = L.append
     _header(a_, p, t, nw, pl, "single-mesh phase")
     a_("// ST: field loads and stores and trace stores carry the nontemporal hint (launch.h)")
-    a_("template <typename R, bool ST>")
+    a_("// STAB: stabilised central flux with face unknowns HF (Section 2.1)")
+    a_("template <typename R, bool ST, bool STAB>")
     a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
-    a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K)")
+    a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K,")
+    a_("    R* __restrict__ HF, const R* __restrict__ SC, R fdt)")
     a_("{")
     a_(f"  __shared__ R wl[{lds_words(p)}];")
     _tile_prologue(a_)
@@ -1150,6 +1196,10 @@ def emit_batch(p: int) -> str:
     a_("  const R sdt = (R)(phase ? sl.dt : -sl.dt);")
     a_("  const R wall = phase ? R(1) : R(-1);")
     a_("  const int K = sl.K;")
+    a_("  constexpr bool STAB = false;  // batches use the central flux")
+    a_("  R* const HF = nullptr;")
+    a_("  const R* const SC = nullptr;")
+    a_("  const R fdt = R(0);")
     a_("  const int tile = bid - tile0[lo];")
     _elem_prologue(a_)
     _phase_body(a_, t, g, Lp, pl, nw)
@@ -1182,10 +1232,14 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f'#include "phase_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_p{p}(const PhaseArgs<R>& a) {{",
-              "  if (a.streaming)",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
+              "  if (a.HF && a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              "  else if (a.HF)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              "  else if (a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  else",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K);",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  return hipGetLastError();",
               "}",
               f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]

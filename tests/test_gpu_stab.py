@@ -1,0 +1,252 @@
+"""Stabilised central flux with face unknowns (Section 2.1): the HIP path against
+the oracle's StabilizedSolver, element by element, through the C-ABI.
+
+Representations: the oracle holds, per face of the mesh, Cartesian coefficient
+vectors b[F, m] of the orthonormal face basis chi_m = psi_m / sqrt(2|F|) (face
+parametrised by its vertices in ascending global id); the library holds, on the
+face's owner side (smaller element index, or the wall element), the tangential
+components sigma[k, m] = b[F, m] . t_k / sqrt(2|F|) with t_1, t_2 the same edge
+vectors.  Entries of non-owner sides are filled with garbage on input: the
+library must neither read nor write them.
+Tolerances: FP64 1e-10, FP32 1e-5 relative to the largest value (as for the
+central flux); runs are compared in the energy norm with the face term.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import Pair, patch, rel_err, sort_tets
+from oracle.stab import StabilizedSolver
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1104_4208_amd as P  # noqa: E402
+
+ALPHA0 = 1.0
+
+
+class StabPair(Pair):
+    """Pair with the oracle's stabilised solver and face-unknown conversions."""
+
+    def __init__(self, verts, tets, p, eps=None, mu=None):
+        super().__init__(verts, tets, p, eps, mu)
+        self.s = StabilizedSolver(oracle.build_mesh(self.verts, sort_tets(tets)), p, eps, mu, alpha0=ALPHA0)
+        self.NF = self.s.NF
+        self.K = self.s.K
+        self.owner = []
+        self.T = []
+        for key, sd in zip(self.s.faces, self.s.sides):
+            self.owner.append(min(sd))  # (element, local face) of the smaller element index
+            w0, w1, w2 = (self.verts[v] for v in key)
+            self.T.append(np.stack([w1 - w0, w2 - w0]))  # (2,3)
+
+    def lib_faces(self, b, garbage=None):
+        """Oracle b (nF, NF, 3) -> library layout (2, NF, 4, K)."""
+        out = np.full((2, self.NF, 4, self.K), np.nan) if garbage is None else garbage.copy()
+        for i, (e, f) in enumerate(self.owner):
+            sc = 1.0 / math.sqrt(2.0 * self.s.area[i])
+            out[:, :, f, e] = (b[i] @ self.T[i].T).T * sc  # (2, NF)
+        return out
+
+    def oracle_faces(self, sig):
+        """Library layout -> oracle b (tangential vectors from the owner's sigma)."""
+        b = np.empty((self.s.nF, self.NF, 3))
+        for i, (e, f) in enumerate(self.owner):
+            T = self.T[i]
+            dual = np.linalg.solve(T @ T.T, T)  # rows t^k with t^k . t_l = delta
+            b[i] = math.sqrt(2.0 * self.s.area[i]) * (sig[:, :, f, e].T @ dual)
+        return b
+
+    def random_faces(self, rng):
+        """Random tangential face unknowns."""
+        b = rng.standard_normal((self.s.nF, self.NF, 3))
+        return b - np.einsum("fmd,fd->fm", b, self.s.nu)[:, :, None] * self.s.nu[:, None, :]
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+MESHES = {
+    "one": lambda rng: synth.single_tet(np.array([[0.1, 0, 0], [1, 0.2, 0], [0, 1.1, 0.1], [0.2, 0.1, 0.9]])),
+    "two_unsorted": lambda rng: synth.two_tets(rng),
+    "cube1": lambda rng: synth.kuhn_mesh(1),
+    "jit2": lambda rng: synth.kuhn_mesh(2, 0.1, rng),
+    "jit3_ragged": lambda rng: synth.kuhn_mesh(3, 0.1, rng),
+}
+
+
+def _mesh(name, p, dtype, seed):
+    rng = np.random.default_rng(seed)
+    verts, tets = MESHES[name](rng)
+    K = tets.shape[0]
+    eps, mu = rng.uniform(1, 4, K), rng.uniform(1, 2, K)
+    pr = StabPair(verts, tets, p, eps, mu)
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, mu).set_stab_alpha(ALPHA0)
+    return rng, pr, m
+
+
+def owner_mask(pr):
+    mask = np.zeros((4, pr.K), bool)
+    for e, f in pr.owner:
+        mask[f, e] = True
+    return mask
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mesh", list(MESHES))
+def test_apply_stab_parity(mesh, p, dtype):
+    if dtype == "f64" and p > P.max_order(P.DGM_F64):
+        pytest.skip("order not compiled for FP64")
+    if p >= 5 and mesh == "jit3_ragged":
+        pytest.skip("covered at lower orders; keeps the oracle fast")
+    rng, pr, m = _mesh(mesh, p, dtype, 300 + p)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    E = rng.standard_normal((pr.K, pr.s.N, 3))
+    H = rng.standard_normal((pr.K, pr.s.N, 3))
+    b = pr.random_faces(rng)
+    garbage = rng.standard_normal((2, pr.NF, 4, pr.K)) * 1e3
+    HFg = dev(pr.lib_faces(b, garbage), tdt)
+    before = host(HFg)
+    dE, dH, dHF = m.apply_stab(dev(pr.to_cov(E), tdt), dev(pr.to_cov(H), tdt), HFg)
+    assert np.array_equal(host(HFg), before)  # input untouched
+    ref_dE = pr.to_cov(pr.s.rhs_e_stab(H, b))
+    ref_dH = pr.to_cov(pr.s.rhs_h(E))
+    ref_dHF = pr.lib_faces(pr.s.rhs_faces(E), np.zeros((2, pr.NF, 4, pr.K)))
+    got_dHF = host(dHF)
+    mask = owner_mask(pr)
+    assert np.all(got_dHF[:, :, ~mask] == 0.0)  # entries of non-owner sides are zero
+    errs = (rel_err(host(dE), ref_dE), rel_err(host(dH), ref_dH), rel_err(got_dHF, ref_dHF))
+    print(f"stab {mesh} p={p} {dtype}: dE {errs[0]:.2e} dH {errs[1]:.2e} dHF {errs[2]:.2e}")
+    assert max(errs) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_step_stab_run_against_oracle(dtype, tol):
+    """TE101 on the jittered 48-tet cube, p = 3, eps in {1, 4}: 60 steps of the
+    stabilised leapfrog against the oracle's, with the stabilised invariant Q."""
+    rng = np.random.default_rng(31)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K, p = tets.shape[0], 3
+    eps = rng.choice([1.0, 4.0], size=K)
+    pr = StabPair(verts, tets, p, eps, None)
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, None).set_stab_alpha(ALPHA0)
+    s = pr.s
+    E = s.project(synth.te101().E)
+    H = np.zeros_like(E)
+    b = s.zeros_faces()
+    dt = 1.0 / math.sqrt(s.spectral_radius_stab(40, synth.splitmix64(31, E.size)))
+    Eg, Hg = dev(pr.to_cov(E), dtype), dev(pr.to_cov(H), dtype)
+    HFg = dev(pr.lib_faces(b, np.zeros((2, pr.NF, 4, K))), dtype)
+    W0o, Q0o = s.energy_stab(E, H, b), s.leapfrog_invariant_stab(E, H, b, dt)
+    W0, Q0 = m.energy_stab(Eg, Hg, HFg, dt=dt)
+    etol = 1e-10 if dtype == torch.float64 else 1e-6  # FP32: the initial state is rounded
+    assert abs(W0 - W0o) < etol * W0o and abs(Q0 - Q0o) < etol * Q0o
+    worst, drift = 0.0, 0.0
+    for blk in range(6):
+        m.step_stab(Eg, Hg, HFg, dt, 10)
+        E, H, b = s.step_stab(E, H, b, dt, 10)
+        Eo, Ho, bo = pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), pr.oracle_faces(host(HFg))
+        num = s.mass_dot(Eo - E, Eo - E, "E") + s.mass_dot(Ho - H, Ho - H, "H") + s.face_dot(bo - b, bo - b)
+        den = s.mass_dot(E, E, "E") + s.mass_dot(H, H, "H") + s.face_dot(b, b)
+        worst = max(worst, math.sqrt(num / den))
+        _, Q = m.energy_stab(Eg, Hg, HFg, dt=dt)
+        drift = max(drift, abs(Q - Q0) / Q0)
+    print(f"stab run {dtype}: worst energy-norm error {worst:.2e}, Q drift {drift:.2e}, face energy "
+          f"{0.5 * s.face_dot(b, b) / W0o:.2e} of W")
+    assert worst < tol
+    assert drift < (1e-12 if dtype == torch.float64 else 1e-6)
+    assert s.face_dot(b, b) > 0
+
+
+def test_estimate_dt_stab_matches_oracle():
+    """The power iteration approaches the largest eigenvalue of the stabilised
+    second-order operator from below: within 1e-3 of the oracle's assembled value
+    after 200 iterations, and above the central flux's."""
+    verts, tets = synth.kuhn_mesh(1)
+    pr = StabPair(verts, tets, 3)
+    Ah, Af, Ae, Ab = pr.s.assemble_stab()
+    rho_exact = float(np.linalg.eigvals(-(Ae @ Ah + Ab @ Af)).real.max())
+    m = P.Mesh(verts, tets).set_order(3).set_stab_alpha(ALPHA0)
+    dt, est = m.estimate_dt_stab(cfl=0.5, iters=200, seed=5)
+    _, rho_c = m.estimate_dt(cfl=0.5, iters=200, seed=5)
+    print(f"stabilised rho: library {est:.8e}, assembled oracle {rho_exact:.8e}; central {rho_c:.6e}")
+    assert rho_exact * (1 - 1e-3) < est < rho_exact * (1 + 1e-12)
+    assert abs(dt - 0.5 * 2 / math.sqrt(est)) < 1e-15
+    assert est > rho_c  # the face term raises the spectral radius
+
+
+def test_stab_requires_alpha_and_checks_buffers():
+    verts, tets = synth.kuhn_mesh(1)
+    m = P.Mesh(verts, tets).set_order(2)
+    E = m.zeros(torch.float64)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.step_stab(E, m.zeros(torch.float64), m.face_zeros(torch.float64), 1e-3, 1)
+    m.set_stab_alpha(2.0)
+    with pytest.raises(P.DGMError):
+        m.step_stab(E, m.zeros(torch.float64), m.face_zeros(torch.float32), 1e-3, 1)
+    with pytest.raises(P.DGMError, match="DGM_ERR_ARG"):
+        m.set_stab_alpha(0.0)
+    assert m.num_face_unknowns == 8 * P.num_face_modes(2) * 6
+
+
+def test_full_size_sampled_stab():
+    """One stabilised rate evaluation on the 16^3 x 6 jittered cube at p = 6 (FP32),
+    checked on sampled elements against the oracle on their patch meshes."""
+    rng = np.random.default_rng(66)
+    n, p = 16, 6
+    verts, tets = synth.kuhn_mesh(n, 0.1, rng)
+    K = tets.shape[0]
+    N, NF = P.num_modes(p), P.num_face_modes(p)
+    eps = rng.choice([1.0, 4.0], size=K)
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, None).set_stab_alpha(ALPHA0)
+    Ecov = rng.standard_normal((3, N, K)).astype(np.float32)
+    Hcov = rng.standard_normal((3, N, K)).astype(np.float32)
+    sig = rng.standard_normal((2, NF, 4, K)).astype(np.float32)
+    dE, dH, dHF = m.apply_stab(dev(Ecov, torch.float32), dev(Hcov, torch.float32), dev(sig, torch.float32))
+    dE, dH, dHF = host(dE), host(dH), host(dHF)
+    centers = np.unique(np.concatenate([rng.integers(0, K, 8), [0, K - 1]]))
+    keep, ptets, pos = patch(tets, centers)
+    pr = StabPair(verts, ptets, p, eps[keep], None)
+    # the patch's face unknowns from the full mesh's owner sides (owner: smaller global index)
+    full_owner = {}
+    ts = sort_tets(tets)
+    for key, sd in zip(pr.s.faces, pr.s.sides):
+        glob = sorted((int(keep[e]), f) for e, f in sd)
+        full_owner[key] = glob[0]
+    b = np.zeros((pr.s.nF, NF, 3))
+    for i, key in enumerate(pr.s.faces):
+        ge, gf = full_owner[key]
+        T = pr.T[i]
+        dual = np.linalg.solve(T @ T.T, T)
+        b[i] = math.sqrt(2.0 * pr.s.area[i]) * (sig[:, :, gf, ge].astype(np.float64).T @ dual)
+    Ep = pr.to_phys(Ecov[:, :, keep].astype(np.float64))
+    Hp = pr.to_phys(Hcov[:, :, keep].astype(np.float64))
+    ref_dE = pr.to_cov(pr.s.rhs_e_stab(Hp, b))[:, :, pos]
+    ref_dH = pr.to_cov(pr.s.rhs_h(Ep))[:, :, pos]
+    rf = pr.s.rhs_faces(Ep)
+    errs = [rel_err(dE[:, :, centers], ref_dE), rel_err(dH[:, :, centers], ref_dH)]
+    # dHF on the centers' faces, read at their full-mesh owners
+    got, ref = [], []
+    for ci, c in enumerate(centers):
+        for f in range(4):
+            key = tuple(sorted(int(ts[c, v]) for v in range(4) if v != f))
+            i = pr.s.faces.index(key)
+            ge, gf = full_owner[key]
+            T = pr.T[i]
+            got.append(dHF[:, :, gf, ge])
+            ref.append((rf[i] @ T.T).T / math.sqrt(2.0 * pr.s.area[i]))
+    errs.append(rel_err(np.array(got), np.array(ref)))
+    print(f"stab 16^3 p6 sampled {len(centers)}: dE {errs[0]:.2e} dH {errs[1]:.2e} dHF {errs[2]:.2e}")
+    assert max(errs) < 1e-5
