@@ -17,11 +17,19 @@ traffic is 36 N + 40 bytes per element per launch (read the differentiated
 field, read and write the updated field, 24 B of metric and 16 B of neighbour
 codes); its average duration is measured live with HIP events on the stream it
 is launched on (difference of a long and a one-step run, so the frame
-conversions at the ends cancel).  cpu_baseline: the FP64 oracle timed on a
+conversions at the ends cancel).  roofline.alu: the generator's emitted
+floating-point operations per element and launch against the FP32 vector peak
+without packed FP32.  roofline.traffic and alu.valu_issue_frac: from the committed
+counter summary when it was taken on the current kernel source.  The run then
+continues to the configuration's 500 steps for the drift of the leapfrog
+invariant.  stabilized_flux: the stabilised central flux (Section 2.1) on the same
+mesh.  dense_variant: the p = 8 matrix-core comparison.  serving: the 256-request
+trace, batched against sequential.  cpu_baseline: the FP64 oracle timed on a
 bounded sample of the same workload (smaller cube, same order and recipe); the
-same leg (the only code here that runs the oracle) reports the FP32 error against
-the oracle on that sample, and at p = 8 for the sparse and dense paths, under
-"accuracy".
+same leg (the only code here that runs the oracle) reports under "accuracy" the
+FP32 error against the oracle on that sample, each FP32 workload's recipe over its
+full step count against the oracle's stored run, and the p = 8 operator errors of
+the sparse and dense paths.
 """
 from __future__ import annotations
 
@@ -38,14 +46,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 (the build disables packed FP32 instructions):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
+# VALU instruction issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles, 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+OPCOUNT_FILE = os.path.join(ROOT, "paper_1104_4208_amd", "csrc", "generated", "opcount.json")
 WORKLOAD = dict(workload="pec_cube_cavity_kuhn32_p6_fp32", cells=32, tets=196608, p=6, modes=84,
                 dofs=99090432, jitter=0.1, eps=[1, 4], steps_in_config=500, init="three cavity modes, seed 3")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_p6_cube32_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when the
-    generated p = 6 kernel source differs from the one the counters were taken on."""
+def opcount(p):
+    """Floating-point operations per element of one phase launch, as emitted by the
+    generator (build step)."""
+    with open(OPCOUNT_FILE) as fh:
+        return json.load(fh)["orders"][str(p)]
+
+
+def measured_counters():
+    """The committed counter summary (bytes, VALU instructions per launch) if it was
+    taken on the current generated p = 6 kernel source, else None."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1104_4208_amd", "csrc", "generated", "phase_p6.inc")
@@ -55,7 +76,7 @@ def measured_traffic():
         tr = json.load(fh)
     with open(src, "rb") as fh:
         h = hashlib.sha256(fh.read()).hexdigest()[:16]
-    return tr.get("bytes_per_launch") if tr.get("kernel_source_sha256_16") == h else None
+    return tr if tr.get("kernel_source_sha256_16") == h else None
 
 
 def parse():
@@ -68,8 +89,10 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the p=8 dense matrix-core comparison")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-nmax", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-nmax", type=int, default=24)
+    ap.add_argument("--no-stab", action="store_true", help="skip the stabilised-flux leg")
+    ap.add_argument("--stab-steps", type=int, default=100)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run three plain device copies of this many MiB (scale reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -138,6 +161,7 @@ def oracle_leg(target_seconds: float, dense: bool):
     err = s.rel_error(pr.to_phys(Eg.double().cpu().numpy()), pr.to_phys(Hg.double().cpu().numpy()), E, H)
     acc = {"fp32_vs_oracle_p6_rel_energy_err": err, "steps": n + 1,
            "sample": f"the cpu_baseline sample ({K} tets, p=6), same initial field, dt = {dt}"}
+    acc["config_runs_vs_oracle"] = run_goldens(P, torch, Pair)
     if dense:
         w = synth.WORKLOADS["cube24_p8_dense"]
         d = synth.build_workload(w)
@@ -156,6 +180,84 @@ def oracle_leg(target_seconds: float, dense: bool):
             acc[f"p8_apply_rel_err_vs_oracle_{name}"] = rel_err(dE[:, :, centers].double().cpu().numpy(), ref)
         acc["p8_sample"] = f"dE = rate(random H) on {len(centers)} elements of the 24^3 x 6 mesh, oracle on patch meshes"
     return base, acc
+
+
+def run_goldens(P, torch, Pair):
+    """Each FP32 workload's recipe over its full step count on the 4^3-cell cube that the
+    oracle ran (tests/golden/run_<name>.npz, written by the oracle alone): final energy-norm
+    error of the library against the oracle and the drift of the leapfrog invariant Q."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("make_run_goldens",
+                                                  os.path.join(ROOT, "tests", "golden", "make_run_goldens.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    out = {}
+    for name, label in (("cfg2", "16cube_p4_1000_steps_recipe"), ("cfg3", "32cube_p6_500_steps_recipe"),
+                        ("cfg4", "24cube_p8_200_steps_recipe")):
+        path = os.path.join(ROOT, "tests", "golden", f"run_{name}.npz")
+        if not os.path.exists(path):
+            continue
+        with np.load(path, allow_pickle=False) as z:
+            g = {k: z[k] for k in z.files}
+        r, verts, tets, eps, mu, s, E, H = mg.setup(name)
+        pr = Pair(verts, tets, r["p"], eps, mu)
+        dt = float(g["dt"])
+        m = P.Mesh(verts, tets).set_order(r["p"]).set_material(eps, mu)
+        Eg = torch.tensor(np.ascontiguousarray(pr.to_cov(E)), dtype=torch.float32, device="cuda")
+        Hg = torch.tensor(np.ascontiguousarray(pr.to_cov(H)), dtype=torch.float32, device="cuda")
+        _, Q0 = m.energy(Eg, Hg, dt=dt)
+        m.step(Eg, Hg, dt, int(g["steps"]))
+        _, Q1 = m.energy(Eg, Hg, dt=dt)
+        err = pr.s.rel_error(pr.to_phys(Eg.double().cpu().numpy()), pr.to_phys(Hg.double().cpu().numpy()),
+                             g["E_end"], g["H_end"])
+        out[label] = {"p": r["p"], "steps": int(g["steps"]), "tets": int(tets.shape[0]),
+                      "fp32_rel_energy_err_vs_oracle": err, "Q_rel_drift": abs(Q1 - Q0) / Q0}
+    return out
+
+
+def stab_leg(w, d, E0, steps: int):
+    """Stabilised central flux with face unknowns (alpha = p^2) on the benchmark mesh:
+    time per step of dgm_step_stab (FP32), the drift of its invariant, and its algorithmic
+    traffic: the central phases' 72 N + 80 bytes per element-step plus the face unknowns
+    (each face's 2 NF values read and written in the H phase, read in the E phase; two faces
+    per element) and the owner's 2x2 update matrix (16 B per face)."""
+    import torch
+
+    import paper_1104_4208_amd as P
+
+    K, p = d["tets"].shape[0], w.p
+    N, NF = P.num_modes(p), P.num_face_modes(p)
+    m = P.Mesh(d["verts"], d["tets"]).set_order(p).set_material(d["eps"], d["mu"]).set_stab_alpha(1.0)
+    dt, rho = m.estimate_dt_stab(cfl=0.5, iters=20, seed=w.seed)
+    E = torch.tensor(np.ascontiguousarray(E0), dtype=torch.float32, device="cuda")
+    H = torch.zeros_like(E)
+    HF = m.face_zeros(torch.float32)
+    _, Q0 = m.energy_stab(E, H, HF, dt=dt)
+    m.step_stab(E, H, HF, dt, 5)
+
+    def timed(nsteps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        m.step_stab(E, H, HF, dt, nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one = min(timed(1) for _ in range(3))
+    t = timed(steps)
+    _, Q1 = m.energy_stab(E, H, HF, dt=dt)
+    step_s = (t - one) / (steps - 1)
+    bytes_step = K * (72 * N + 80 + 2 * 3 * 2 * NF * 4 + 2 * 16)
+    del E, H, HF, m
+    torch.cuda.empty_cache()
+    return {"workload": "pec_cube_cavity_kuhn32_p6_fp32_stabilised", "alpha": f"p^2 = {p * p}", "dt": dt,
+            "rho": rho, "steps": steps, "ms_per_step": step_s * 1e3,
+            "dof_updates_per_s": 6 * N * K / step_s,
+            "algorithmic_bytes_per_element_step": 72 * N + 80 + 2 * 3 * 2 * NF * 4 + 2 * 16,
+            "hbm_frac": bytes_step / step_s / (HBM_PEAK_GBS * 1e9),
+            "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps + 8}
 
 
 def dense_comparison(steps: int):
@@ -270,7 +372,22 @@ def main():
     bytes_launch = K * (36 * N + 40)
     achieved = bytes_launch / phase_s / 1e9
     value = 6 * N * K * a.steps / wall
-    traffic = measured_traffic()
+    ctr = measured_counters()
+    traffic = ctr.get("bytes_per_launch") if ctr else None
+    oc = opcount(p)
+    flops_launch = K * oc["with_traces"]
+    alu = {"flops_per_element_phase": oc["with_traces"], "flops_per_launch": flops_launch,
+           "flops_per_dof_update": 2 * oc["with_traces"] / (6 * N),
+           "achieved": flops_launch / phase_s / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": flops_launch / phase_s / 1e12 / FP32_PEAK_TFLOPS,
+           "peak_note": "FP32 vector FMA without packed FP32 (switched off in this build): "
+                        "256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz",
+           "count_note": "emitted multiplies and adds (FMA = 2) per element, including the x=0/y=0 trace "
+                         f"jobs ({oc['trace_stage_recomputed_faces']} flops) that run only in tiles with an "
+                         "off-tile neighbour across those faces"}
+    if ctr and ctr.get("valu_insts_per_launch"):
+        alu["valu_insts_per_launch"] = ctr["valu_insts_per_launch"]
+        alu["valu_issue_frac"] = ctr["valu_insts_per_launch"] / VALU_ISSUE_PER_S / phase_s
     out = {
         "metric": "DOF-updates/sec & %HBM roofline at p=6 (FP32 vs FP64 oracle err); serving p50/p99",
         "value": value,
@@ -287,20 +404,31 @@ def main():
         "config": dict(WORKLOAD, dt=dt, rho=rho),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "dgm_phase_p6<float, true>", "phase_us": phase_s * 1e6, "bytes_per_launch": bytes_launch},
+                     "kernel": "dgm_phase_p6<float, true, false>", "phase_us": phase_s * 1e6,
+                     "bytes_per_launch": bytes_launch, "alu": alu},
         "energy": {"W0": W0, "Q0": Q0, "Q_end": Q1, "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps_done},
     }
+    # the config's full 500 steps at full size: drift of the leapfrog invariant (FP32 state,
+    # FP64 reduction) over the whole run, after the timed region
+    rest = max(0, w.steps - steps_done)
+    if rest:
+        m.step(E, H, dt, rest)
+    W2, Q2 = m.energy(E, H, dt=dt)
+    out["energy"]["Q_rel_drift_full_run"] = abs(Q2 - Q0) / Q0
+    out["energy"]["steps_full_run"] = steps_done + rest
     del E, H
     torch.cuda.empty_cache()
+    if not a.no_stab:
+        out["stabilized_flux"] = stab_leg(w, d, E0, a.stab_steps)
     if not a.no_dense:
         out["dense_variant"] = dense_comparison(a.dense_steps)
     if not a.no_serve:
         from paper_1104_4208_amd import serve
 
         rep = serve.serve_report(num=a.serve_requests, budget_gib=2.0, chunk=20, n_range=(4, a.serve_nmax))
-        rep["note"] = ("reduced trace of the serving workload (same recipe: Poisson arrivals at 50/s, p in 2..8, "
-                       "eps in {1,2,4}, steps in 200..2000, jitter 0.1 h) with n <= serve_nmax so the default run stays "
-                       "short; `python -m paper_1104_4208_amd.serve` runs the full 256-request trace")
+        rep["note"] = ("serving trace: Poisson arrivals at 50/s, n in 4..serve_nmax, p in 2..8, eps in {1,2,4}, "
+                       "steps in 200..2000, jitter 0.1 h, 2 GiB admission budget, 20 steps per batched launch; "
+                       "sequential = the same trace solved one request at a time with dgm_step")
         out["serving"] = rep
     if not a.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = oracle_leg(a.cpu_seconds, dense=not a.no_dense)

@@ -1436,6 +1436,10 @@ struct dgm_batch {
   std::vector<int> h_tile0[DGM_MAX_ORDER_F32 + 1];
   int h_n[DGM_MAX_ORDER_F32 + 1] = {};
   hipStream_t cap_stream = nullptr;
+  // one capture branch per order (default priority), forked from and joined into cap_stream
+  hipStream_t br_stream[DGM_MAX_ORDER_F32 + 1] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[DGM_MAX_ORDER_F32 + 1] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
@@ -1456,12 +1460,22 @@ int batch_capture(dgm_batch* b) {
     if ((b->live_orders & (1u << p)) && !kBatchF32[p])
       return fail(DGM_ERR_ARG, "batched kernel of order " + std::to_string(p) + " not built");
   if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  if (!b->fork_ev) HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  for (int p = 1; p <= DGM_MAX_ORDER_F32; ++p) {
+    if (b->cap_tiles[p] <= 0 || !(b->live_orders & (1u << p))) continue;
+    if (!b->br_stream[p]) HIP_TRY(hipStreamCreateWithFlags(&b->br_stream[p], hipStreamNonBlocking));
+    if (!b->join_ev[p]) HIP_TRY(hipEventCreateWithFlags(&b->join_ev[p], hipEventDisableTiming));
+  }
+  // The slots of different orders are independent: each order's chain of half steps is
+  // its own branch of the graph (forked from the capture stream, joined back at the end),
+  // so the orders' kernels overlap on the device instead of running one after another.
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t err = hipSuccess;
-  for (int sub = 0; sub < b->chunk && err == hipSuccess; ++sub)
-    for (int phase = 0; phase < 2 && err == hipSuccess; ++phase)
-      for (int p = 1; p <= DGM_MAX_ORDER_F32 && err == hipSuccess; ++p) {
-        if (b->cap_tiles[p] <= 0 || !(b->live_orders & (1u << p))) continue;
+  hipError_t err = hipEventRecord(b->fork_ev, b->cap_stream);
+  for (int p = 1; p <= DGM_MAX_ORDER_F32 && err == hipSuccess; ++p) {
+    if (b->cap_tiles[p] <= 0 || !(b->live_orders & (1u << p))) continue;
+    err = hipStreamWaitEvent(b->br_stream[p], b->fork_ev, 0);
+    for (int sub = 0; sub < b->chunk && err == hipSuccess; ++sub)
+      for (int phase = 0; phase < 2 && err == hipSuccess; ++phase) {
         BatchArgs a;
         a.slots = b->d_slots[p];
         a.tile0 = b->d_tile0[p];
@@ -1470,9 +1484,12 @@ int batch_capture(dgm_batch* b) {
         a.substep = sub;
         a.blocks = b->cap_tiles[p];
         a.streaming = b->streaming;
-        a.stream = b->cap_stream;
+        a.stream = b->br_stream[p];
         err = kBatchF32[p](a);
       }
+    if (err == hipSuccess) err = hipEventRecord(b->join_ev[p], b->br_stream[p]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(b->cap_stream, b->join_ev[p], 0);
+  }
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
   if (err != hipSuccess) return fail(DGM_ERR_HIP, std::string("batched launch capture: ") + hipGetErrorString(err));
@@ -1500,6 +1517,11 @@ int dgm_batch_destroy(dgm_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (int p = 0; p <= DGM_MAX_ORDER_F32; ++p) {
+    if (b->br_stream[p]) (void)hipStreamDestroy(b->br_stream[p]);
+    if (b->join_ev[p]) (void)hipEventDestroy(b->join_ev[p]);
+  }
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
   for (int p = 0; p <= DGM_MAX_ORDER_F32; ++p) {
     (void)hipFree(b->d_slots[p]);
     (void)hipFree(b->d_tile0[p]);

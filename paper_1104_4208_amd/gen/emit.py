@@ -33,6 +33,16 @@ import numpy as np
 from . import tables as TB
 
 
+# Floating-point operations written into the kernel being emitted (multiplies and adds;
+# an FMA counts two), per element: every wave's jobs together cover each element once.
+FLOPS = [0]
+OPCOUNT = {}
+
+
+def _count(n):
+    FLOPS[0] += n
+
+
 def _lit(v: float) -> str:
     """Exact literal of an FP64 table entry, rounded once to the kernel's type R."""
     if v == 1.0:
@@ -44,9 +54,12 @@ def _lit(v: float) -> str:
 
 def _fma(acc, coef, x):
     if coef == 1.0:
+        _count(1)
         return f"{acc} += {x};"
     if coef == -1.0:
+        _count(1)
         return f"{acc} -= {x};"
+    _count(2)
     return f"{acc} += {_lit(coef)} * {x};"
 
 
@@ -472,6 +485,7 @@ def trace_strides(NF: int):
 
 def _lin(terms):
     """Expression of a linear combination [(coef, name)] with literal coefficients."""
+    _count(len(terms) - 1 + sum(1 for c, _ in terms if c not in (1.0, -1.0)))
     out = []
     for c, v in terms:
         if c == 1.0:
@@ -709,6 +723,7 @@ def _lift_job(a_, t, Lp, rows, ind):
                         terms.append(f"{_lit(c0)} * {x[0]}")
                     if c1 != 0.0:
                         terms.append(f"{_lit(c1)} * {x[1]}")
+                    _count(2 * len(terms) - 1)
                     out.append(f"const R g{k} = {' + '.join(terms)};")
                     for j, b in enumerate(rows):
                         c = t.T[f][m, b]
@@ -736,6 +751,7 @@ def _lift_job(a_, t, Lp, rows, ind):
     for j, b in enumerate(rows):
         for k in range(3):
             old = f"vo{k}_{j}" if early else f"ldf<ST>(&V[({k * N + b}) * Ks + el])"
+            _count(2)
             a_(ind + f"  acc{k}_{j} = {old} + sdt * acc{k}_{j};")
     a_(ind + "  if (act) {")
     for j, b in enumerate(rows):
@@ -799,6 +815,7 @@ def _stage_parts(t, nw, X, mp):
         ld.append(f"const R s{i}_0 = ldf<ST>(&{X}[(size_t)a{i} * Ks + ez]), "
                   f"s{i}_1 = ldf<ST>(&{X}[(size_t)({N} + a{i}) * Ks + ez]), "
                   f"s{i}_2 = ldf<ST>(&{X}[(size_t)({2 * N} + a{i}) * Ks + ez]);")
+        _count(15)
         st.append(f"wl[a{i} * {LANES} + lz] = n00 * s{i}_0 + n01 * s{i}_1 + n02 * s{i}_2;")
         st.append(f"wl[({N} + a{i}) * {LANES} + lz] = n01 * s{i}_0 + n11 * s{i}_1 + n12 * s{i}_2;")
         st.append(f"wl[({2 * N} + a{i}) * {LANES} + lz] = n02 * s{i}_0 + n12 * s{i}_1 + n22 * s{i}_2;")
@@ -871,6 +888,7 @@ def _jump_lines(t, nw):
             for f in range(4):
                 L.append(f"    const R ow{f} = wl[((({f} * 2 + k) * {NF}) + m) * {LANES} + lane];")
                 L.append(f"    const R nv{f} = wl[(((gf{f} * 2 + k) * {NF}) + m) * {LANES} + (nb{f} & 63)];")
+            _count(4)
             for f in range(4):
                 L.append(f"    R jf{f} = code{f} < 0 ? cw * ow{f} : (in{f} ? nv{f} : t{i}_{f}_{jj}) - ow{f};")
             # stabilised flux, E phase: the face unknowns (held by the face's owner side)
@@ -1062,6 +1080,7 @@ def _phase_body(a_, t, g, Lp, pl, nw):
         for rows in pl["out"][w]:
             _lift_job(a_, t, Lp, rows, "    ")
         a_("  }")
+    FLOPS_NO_TRACE = FLOPS[0]
     a_("  if (Tout == nullptr) return;")
     a_("  // E: the updated rows (still in registers) in the derivative frame into LDS")
     a_("  {")
@@ -1072,6 +1091,7 @@ def _phase_body(a_, t, g, Lp, pl, nw):
         a_(f"    if (wave == {w}) {{")
         for rows in pl["out"][w]:
             for j, b in enumerate(rows):
+                _count(15)
                 a_(f"      wl[{b} * {LANES} + lane] = n00 * acc0_{j} + n01 * acc1_{j} + n02 * acc2_{j};")
                 a_(f"      wl[{N + b} * {LANES} + lane] = n01 * acc0_{j} + n11 * acc1_{j} + n12 * acc2_{j};")
                 a_(f"      wl[{2 * N + b} * {LANES} + lane] = n02 * acc0_{j} + n12 * acc1_{j} + n22 * acc2_{j};")
@@ -1079,7 +1099,9 @@ def _phase_body(a_, t, g, Lp, pl, nw):
     a_("  }")
     a_("  __syncthreads();")
     a_("  // F: its traces for the next phase")
+    before_f = FLOPS[0]
     _trace_stage(a_, t, g, pl, nw)
+    return dict(no_traces=FLOPS_NO_TRACE, with_traces=FLOPS[0], trace_stage=FLOPS[0] - before_f)
 
 
 def _kernel_setup(p):
@@ -1138,7 +1160,17 @@ def emit_phase(p: int) -> str:
     a_(f"  __shared__ R wl[{lds_words(p)}];")
     _tile_prologue(a_)
     _elem_prologue(a_)
-    _phase_body(a_, t, g, Lp, pl, nw)
+    FLOPS[0] = 0
+    cnt = _phase_body(a_, t, g, Lp, pl, nw)
+    # the recomputed faces' trace jobs in stage F run only in tiles with an off-tile
+    # neighbour across that face: their share is reported apart
+    FLOPS[0] = 0
+    for w in range(nw):
+        for (f, k, rows) in pl["trace"][w]:
+            if f in RECOMPUTED:
+                _trace_job(lambda x: None, t, g, f, k, rows, "", sink=lambda *a: None)
+    cnt["trace_stage_recomputed_faces"] = FLOPS[0]
+    OPCOUNT[p] = dict(cnt, N=t.N, NF=t.NF, waves=nw)
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -1295,6 +1327,14 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     lines += launcher_tables(orders)
     _write_if_changed(os.path.join(outdir, "frame.inc"), "\n".join(lines) + "\n")
     _write_if_changed(os.path.join(outdir, "tables.inc"), emit_host_tables(orders))
+    import json
+
+    _write_if_changed(os.path.join(outdir, "opcount.json"), json.dumps(
+        {"note": "floating-point operations (multiply and add; an FMA counts two) per element and phase "
+                 "launch as emitted: no_traces (rate only), with_traces (the step's phase: also the traces of "
+                 "the updated field), trace_stage_recomputed_faces (part of the trace stage that runs only "
+                 "in tiles with an off-tile neighbour across the x = 0 or y = 0 face)",
+         "orders": {str(p): OPCOUNT[p] for p in orders}}, indent=1) + "\n")
     return units
 
 
