@@ -16,6 +16,7 @@ Contents
   stab    -- the stabilised central flux with face unknowns H^F (Section 2.1):
              per-face tangential unknowns, their update from the tangential
              jump of E, the extra E-equation term, energies, assembly.
+  mixed   -- mixed orders, E of degree p+1 and H of degree p (Section 2).
 
 Pins (tests/test_oracle.py) tie each function to something other than
 itself: closed-form norms, orthogonality, integration by parts, exact
@@ -24,7 +25,10 @@ exact conservation of the leapfrog invariant, the scalar stability
 threshold, and h-convergence to the exact PEC cube eigenmodes
 (tests/test_oracle_stab.py for the stabilised flux: skew-symmetry, the
 null-space dimension in closed form, cavity eigenvalues kept and spurious
-ones removed, reduction to the central flux, exact leapfrog invariant).
+ones removed, reduction to the central flux, exact leapfrog invariant;
+tests/test_oracle_mixed.py for mixed orders: skew-symmetry, exact curls of
+global polynomials, exact invariant, no spurious mode below the first cavity
+mode, TE101 convergence).
 
 Parity unpinned: the paper's own experiments (the spherical resonator of
 Section 2.2 and the timings of Section 3.5) cannot be reproduced here: the
@@ -33,4 +37,5 @@ meshes and the reference data are not available.
 from .basis import eval_basis, mode_list, num_modes, tet_quadrature, triangle_quadrature  # noqa: F401
 from .dg import Mesh, Solver, build_mesh  # noqa: F401
 from .stab import StabilizedSolver  # noqa: F401
+from .mixed import MixedSolver  # noqa: F401
 from .jacobi import djacobi, gauss_jacobi, jacobi  # noqa: F401
