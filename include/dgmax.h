@@ -174,6 +174,20 @@ int dgm_energy(dgm_mesh* mesh, int dtype, const void* E, const void* H, const vo
 int dgm_estimate_dt(dgm_mesh* mesh, double cfl, int iters, uint64_t seed, double* dt, double* rho_out,
                     hipStream_t stream);
 
+/* Mixed orders (Section 2): E of degree pE = pH + 1 and H of degree pH, the pairing
+ * the paper chooses because all derivatives fall on E and its test functions
+ * (pE == pH is dgm_set_order(mesh, pH)).  E-shaped arrays (E, dE, the probe weights)
+ * then have N_E = dgm_num_modes(pE) modes per component and H-shaped ones N_H; the
+ * curl maps the N_E modes of E into the N_H rows of H and back, with the lift of each
+ * field's face traces (degree of that field) into the other's rows.  dgm_apply_curl,
+ * dgm_step, dgm_step_probe, dgm_step_noalloc, dgm_energy and dgm_estimate_dt accept
+ * mixed orders; the stabilised flux, the dense variant and batch slots need equal
+ * orders (DGM_ERR_STATE).  Built for pH = 1 .. max order - 1 (FP64: pE up to the
+ * FP64 maximum).  Errors: DGM_ERR_ARG for another pair or one not built. */
+int dgm_set_orders(dgm_mesh* mesh, int pE, int pH);
+/* The orders set on the mesh (both 0 before dgm_set_order / dgm_set_orders). */
+int dgm_orders(const dgm_mesh* mesh, int* pE, int* pH);
+
 /* Stabilised central flux with face unknowns H^F (Section 2.1), the paper's
  * recommended method: it keeps the discrete energy and removes the spurious
  * modes of the central flux.  Besides E and H the state holds, on every face, a

@@ -232,7 +232,8 @@ __global__ void scale_kernel(R* __restrict__ X, size_t n, const double* __restri
 // ---------------------------------------------------------------- mesh
 struct dgm_mesh {
   int64_t K = 0;
-  int p = 0;
+  int p = 0;    // order of H (the mesh's order); E has order pE = p or p + 1 (mixed orders)
+  int pE = 0;
   std::vector<double> F;   // (K,9) row-major 3x3, columns v1-v0, v2-v0, v3-v0 (sorted vertices)
   std::vector<double> J;   // signed det F
   std::vector<int> nbr;    // (4,K)
@@ -271,6 +272,14 @@ struct dgm_mesh {
 
 namespace {
 
+// Order of field fld (0: E, 1: H); they differ only with mixed orders (dgm_set_orders).
+int ford(const dgm_mesh* m, int fld) { return fld == 0 ? m->pE : m->p; }
+bool mixed(const dgm_mesh* m) { return m->pE != m->p; }
+size_t field_len(const dgm_mesh* m, int fld) { return (size_t)3 * num_modes(ford(m, fld)) * (size_t)m->K; }
+size_t mesh_step_bytes(const dgm_mesh* m, size_t rsize) {
+  return (field_len(m, 0) + field_len(m, 1) + trace_words(m->K, m->pE) + trace_words(m->K, m->p)) * rsize;
+}
+
 int ensure_scratch(dgm_mesh* m, size_t bytes) {
   if (m->scratch_bytes >= bytes) return DGM_OK;
   if (m->d_scratch) HIP_TRY(hipFree(m->d_scratch));
@@ -284,8 +293,8 @@ int ensure_scratch(dgm_mesh* m, size_t bytes) {
 // Trace buffers of both fields (E, then H) in precision R, grown on demand.
 template <typename R>
 int ensure_traces(dgm_mesh* m, R** TE, R** TH) {
-  const size_t per = trace_words(m->K, m->p);
-  const size_t bytes = 2 * per * sizeof(R);
+  const size_t per = trace_words(m->K, m->pE);
+  const size_t bytes = (per + trace_words(m->K, m->p)) * sizeof(R);
   if (m->T_bytes < bytes) {
     if (m->d_T) HIP_TRY(hipFree(m->d_T));
     m->d_T = nullptr;
@@ -421,6 +430,8 @@ template <> double* Minvdev<double>(dgm_mesh* m, int fld) { return m->d_Minv64[f
 
 hipError_t phase(const PhaseArgs<float>& a, int p) { return kPhaseF32[p](a); }
 hipError_t phase(const PhaseArgs<double>& a, int p) { return kPhaseF64[p](a); }
+hipError_t mix(const PhaseArgs<float>& a, int p, int dir) { return kMixF32[p](a, dir); }
+hipError_t mix(const PhaseArgs<double>& a, int p, int dir) { return kMixF64[p](a, dir); }
 hipError_t trace(const TraceArgs<float>& a, int p) { return kTraceF32[p](a); }
 hipError_t trace(const TraceArgs<double>& a, int p) { return kTraceF64[p](a); }
 
@@ -432,13 +443,32 @@ bool order_built(int p, int dtype) {
   return p <= DGM_MAX_ORDER_F64 && kPhaseF64[p] != nullptr && kTraceF64[p] != nullptr;
 }
 
+// Mixed orders (H of order p, E of order p + 1): the pair's phase kernels and both orders'
+// trace kernels must be built for dtype.
+bool mixed_built(int p, int dtype) {
+  if (p < 1 || p + 1 > DGM_MAX_ORDER_F32) return false;
+  if (dtype == DGM_F32) return kMixF32[p] != nullptr && kTraceF32[p] != nullptr && kTraceF32[p + 1] != nullptr;
+  return p + 1 <= DGM_MAX_ORDER_F64 && kMixF64[p] != nullptr && kTraceF64[p] != nullptr && kTraceF64[p + 1] != nullptr;
+}
+
 int check_order(dgm_mesh* m, int dtype) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
   if (dtype != DGM_F32 && dtype != DGM_F64) return fail(DGM_ERR_ARG, "dtype must be DGM_F32 or DGM_F64");
   if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
+  if (mixed(m)) {
+    if (!mixed_built(m->p, dtype))
+      return fail(DGM_ERR_ARG, "mixed orders (" + std::to_string(m->pE) + ", " + std::to_string(m->p) +
+                                   ") not compiled for this dtype");
+    return DGM_OK;
+  }
   if (!order_built(m->p, dtype))
     return fail(DGM_ERR_ARG, "order " + std::to_string(m->p) + " not compiled for this dtype (max " +
                                  std::to_string(dtype == DGM_F32 ? DGM_MAX_ORDER_F32 : DGM_MAX_ORDER_F64) + ")");
+  return DGM_OK;
+}
+
+int check_equal_orders(const dgm_mesh* m, const char* what) {
+  if (mixed(m)) return fail(DGM_ERR_STATE, std::string(what) + " needs equal orders for E and H");
   return DGM_OK;
 }
 
@@ -448,7 +478,7 @@ int convert(dgm_mesh* m, R* X, int fld, bool to_stored, hipStream_t s) {
   const R* Msym = to_stored ? Minvdev<R>(m, fld) : Mdev<R>(m, fld);
   const int threads = 256;
   hipLaunchKernelGGL(convert_kernel<R>, dim3((unsigned)((m->K + threads - 1) / threads)), dim3(threads), 0, s, X, Msym,
-                     num_modes(m->p), (int)m->K, to_stored ? 1 : 0, C[0], C[1], C[2], C[3], C[4], C[5], C[6], C[7],
+                     num_modes(ford(m, fld)), (int)m->K, to_stored ? 1 : 0, C[0], C[1], C[2], C[3], C[4], C[5], C[6], C[7],
                      C[8]);
   HIP_TRY(hipGetLastError());
   return DGM_OK;
@@ -471,7 +501,7 @@ int run_trace(dgm_mesh* m, const R* U, int fld, R* T, hipStream_t s) {
   a.K = (int)m->K;
   a.blocks = (int)((m->K + 63) / 64);
   a.stream = s;
-  HIP_TRY(trace(a, m->p));
+  HIP_TRY(trace(a, ford(m, fld)));
   return DGM_OK;
 }
 
@@ -501,12 +531,17 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
   a.wall = fld_u == 0 ? (R)-1 : (R)1;
   a.K = (int)m->K;
   a.blocks = (int)((m->K + 63) / 64);
-  a.streaming = step_bytes(m->K, m->p, sizeof(R)) > kStreamingBytes;
+  a.streaming = mesh_step_bytes(m, sizeof(R)) > kStreamingBytes;
   a.stream = s;
   a.HF = HF;
   a.SC = HF ? SCdev<R>(m) : nullptr;
   a.fdt = (R)fdt;
-  HIP_TRY(phase(a, m->p));
+  if (mixed(m)) {
+    if (HF) return fail(DGM_ERR_STATE, "the stabilised flux needs equal orders");
+    HIP_TRY(mix(a, m->p, fld_u));
+  } else {
+    HIP_TRY(phase(a, m->p));
+  }
   return DGM_OK;
 }
 
@@ -514,7 +549,7 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
 // fld_u = 0: in = E, out = dH;  fld_u = 1: in = H, out = dE.
 template <typename R>
 int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF = nullptr, double fdt = 0.0) {
-  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  const size_t n = field_len(m, fld_u), n_out = field_len(m, 1 - fld_u);
   int rc;
   if ((rc = ensure_scratch(m, n * sizeof(R)))) return rc;
   R* tmp = static_cast<R*>(m->d_scratch);
@@ -523,7 +558,7 @@ int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF 
   HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(R), hipMemcpyDeviceToDevice, s));
   if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
   if ((rc = run_trace<R>(m, tmp, fld_u, T[fld_u], s))) return rc;
-  if ((rc = fill<R>(out, n, (R)0, s))) return rc;
+  if ((rc = fill<R>(out, n_out, (R)0, s))) return rc;
   if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt))) return rc;
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
@@ -555,10 +590,11 @@ struct StepWork {
 // FP64 sum of squares of both fields (any frame), synchronised: finite iff every
 // coefficient is finite (short of overflow in the squares).
 template <typename R>
-int finite_state(const StepWork<R>& ws, const R* E, const R* H, size_t n, int nb, bool* ok, hipStream_t s) {
+int finite_state(const StepWork<R>& ws, const R* E, const R* H, size_t nE, size_t nH, int nb, bool* ok,
+                 hipStream_t s) {
   for (int f = 0; f < 2; ++f) {
     const R* X = f == 0 ? E : H;
-    hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, X, X, n, ws.partial);
+    hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, X, X, f == 0 ? nE : nH, ws.partial);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, ws.partial, nb, ws.res + f);
     HIP_TRY(hipGetLastError());
@@ -593,8 +629,8 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
               const R* w = nullptr, double* d_sig = nullptr, R* HF = nullptr) {
   int rc;
   if (nsteps == 0) return DGM_OK;
-  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
-  const int nb = (int)std::min<size_t>(kDotBlocks, (n + kRedThreads - 1) / kRedThreads);
+  const size_t n = field_len(m, 0), nH = field_len(m, 1);
+  const int nb = (int)std::min<size_t>(kDotBlocks, (std::max(n, nH) + kRedThreads - 1) / kRedThreads);
   const int64_t every = m->check_every;
   R* const TE = ws.TE;
   R* const TH = ws.TH;
@@ -614,7 +650,7 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
     }
     if (every > 0 && ((it + 1) % every == 0 || it + 1 == nsteps)) {
       bool ok = true;
-      if ((rc = finite_state<R>(ws, E, H, n, nb, &ok, s))) return rc;
+      if ((rc = finite_state<R>(ws, E, H, n, nH, nb, &ok, s))) return rc;
       if (!ok) {
         if ((rc = convert<R>(m, E, 0, false, s))) return rc;
         if ((rc = convert<R>(m, H, 1, false, s))) return rc;
@@ -632,7 +668,7 @@ int mdot(dgm_mesh* m, const R* A, const R* B, int fld, double* d_out, hipStream_
   const int nb = (int)((m->K + kRedThreads - 1) / kRedThreads);
   int rc;
   if ((rc = ensure_partial(m, nb))) return rc;
-  hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, A, B, m->d_G[fld], num_modes(m->p),
+  hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, A, B, m->d_G[fld], num_modes(ford(m, fld)),
                      (int)m->K, m->d_partial);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, d_out);
@@ -642,7 +678,7 @@ int mdot(dgm_mesh* m, const R* A, const R* B, int fld, double* d_out, hipStream_
 
 template <typename R>
 int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, double out[2], hipStream_t s) {
-  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  const size_t n = field_len(m, 1), nE = field_len(m, 0);
   int rc;
   if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
   double* d_res = m->d_res;
@@ -650,8 +686,8 @@ int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, dou
   R* hn_buf = nullptr;
   if (!Hq) {
     // H_next = H + dt dH(E); the rate uses the first half of the scratch, H_next the second
-    if ((rc = ensure_scratch(m, 2 * n * sizeof(R)))) return rc;
-    hn_buf = static_cast<R*>(m->d_scratch) + n;
+    if ((rc = ensure_scratch(m, (nE + n) * sizeof(R)))) return rc;
+    hn_buf = static_cast<R*>(m->d_scratch) + nE;
     if ((rc = rate_impl<R>(m, E, hn_buf, 0, s))) return rc;
     hipLaunchKernelGGL(xpay_kernel<R>, dim3(flat_blocks(n)), dim3(kFlatThreads), 0, s, hn_buf, H, n, dt);
     HIP_TRY(hipGetLastError());
@@ -710,14 +746,14 @@ int dense_rate(dgm_mesh* m, DenseOps* d, const float* in, float* out, int fld_u,
 template <typename R>
 int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
   int rc = DGM_OK;
-  const size_t n = (size_t)3 * num_modes(m->p) * m->K;
+  const size_t n = field_len(m, 1), nE = field_len(m, 0);  // x, z hold H; y holds E
   R* x = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), 3 * n * sizeof(R) + 5 * sizeof(double), s));
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), (2 * n + nE) * sizeof(R) + 5 * sizeof(double), s));
   R* const base = x;
-  R* y = x + n;
-  R* z = y + n;
+  R* z = x + n;
+  R* y = z + n;
   // three FP64 dot products after the vectors, aligned to 8 bytes
-  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(z + n) + 7) & ~uintptr_t(7));
+  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(y + nE) + 7) & ~uintptr_t(7));
   const unsigned blocks = flat_blocks(n);
   hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, x, n, (unsigned long long)seed);
   if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "start vector kernel launch failed");
@@ -1127,6 +1163,26 @@ int dgm_set_order(dgm_mesh* m, int p) {
     }
   }
   m->p = p;
+  m->pE = p;
+  return DGM_OK;
+}
+
+int dgm_set_orders(dgm_mesh* m, int pE, int pH) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  if (pE != pH && pE != pH + 1) return fail(DGM_ERR_ARG, "E's order must equal H's or exceed it by one");
+  if (pE == pH) return dgm_set_order(m, pH);
+  if (!mixed_built(pH, DGM_F32))
+    return fail(DGM_ERR_ARG, "mixed orders (" + std::to_string(pE) + ", " + std::to_string(pH) + ") not built");
+  int rc;
+  if ((rc = dgm_set_order(m, pH))) return rc;
+  m->pE = pE;
+  return DGM_OK;
+}
+
+int dgm_orders(const dgm_mesh* m, int* pE, int* pH) {
+  if (!m || !pE || !pH) return fail(DGM_ERR_ARG, "null argument");
+  *pE = m->pE;
+  *pH = m->p;
   return DGM_OK;
 }
 
@@ -1220,6 +1276,7 @@ int dgm_apply_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const v
                    hipStream_t s) {
   int rc = check_order(m, dtype);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
   if (((dH || dHF) && !E) || (dE && (!H || !HF))) return fail(DGM_ERR_ARG, "output requested without its input");
   const void* outs[3] = {dE, dH, dHF};
@@ -1235,6 +1292,7 @@ int dgm_apply_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const v
 int dgm_step_stab(dgm_mesh* m, int dtype, void* E, void* H, void* HF, double dt, int64_t nsteps, hipStream_t s) {
   int rc = check_order(m, dtype);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
   if (!E || !H || !HF || E == H || E == HF || H == HF || nsteps < 0 || !std::isfinite(dt))
     return fail(DGM_ERR_ARG, "bad step arguments");
@@ -1254,6 +1312,7 @@ int dgm_energy_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const 
                     hipStream_t s) {
   int rc = check_order(m, dtype);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
   if (!E || !H || !HF || !out || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad energy arguments");
   return dtype == DGM_F32 ? energy_stab_impl<float>(m, (const float*)E, (const float*)H, (const float*)HF, dt, out, s)
@@ -1264,6 +1323,7 @@ int dgm_estimate_dt_stab(dgm_mesh* m, double cfl, int iters, uint64_t seed, doub
                          hipStream_t s) {
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
   if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
   return m->p <= DGM_MAX_ORDER_F64 ? estimate_stab_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
@@ -1307,8 +1367,9 @@ constexpr size_t kScratchTraceOff = (kScratchResOff + 2 * sizeof(double) + 255) 
 
 // Bytes of the workspace a run on mesh m in precision rsize needs.
 size_t noalloc_bytes(const dgm_mesh* m, size_t rsize) {
-  const size_t per = (trace_words(m->K, m->p) * rsize + 255) & ~size_t(255);
-  return kScratchTraceOff + 2 * per;
+  const size_t pe = (trace_words(m->K, m->pE) * rsize + 255) & ~size_t(255);
+  const size_t ph = (trace_words(m->K, m->p) * rsize + 255) & ~size_t(255);
+  return kScratchTraceOff + pe + ph;
 }
 
 // The workspace laid out as trace buffers and reduction buffers (nothing is allocated;
@@ -1317,7 +1378,7 @@ size_t noalloc_bytes(const dgm_mesh* m, size_t rsize) {
 template <typename R>
 void noalloc_work(const dgm_mesh* m, void* base, StepWork<R>* ws) {
   unsigned char* b = static_cast<unsigned char*>(base);
-  const size_t per = (trace_words(m->K, m->p) * sizeof(R) + 255) & ~size_t(255);
+  const size_t per = (trace_words(m->K, m->pE) * sizeof(R) + 255) & ~size_t(255);
   ws->partial = reinterpret_cast<double*>(b + kScratchPartialOff);
   ws->res = reinterpret_cast<double*>(b + kScratchResOff);
   ws->TE = reinterpret_cast<R*>(b + kScratchTraceOff);
@@ -1371,13 +1432,14 @@ int dgm_estimate_dt(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* d
   if (rc) return rc;
   if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
   // FP64 vectors where the order is compiled in FP64, FP32 vectors (FP64 dots) above it
-  return m->p <= DGM_MAX_ORDER_F64 ? estimate_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
+  return m->pE <= DGM_MAX_ORDER_F64 ? estimate_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
                                    : estimate_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
 }
 
 int dgm_apply_curl_dense(dgm_mesh* m, int prec, const float* E, const float* H, float* dE, float* dH, hipStream_t s) {
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the dense variant"))) return rc;
   if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
   if ((dH && !E) || (dE && !H)) return fail(DGM_ERR_ARG, "output requested without its input");
   if ((dH && (dH == E || dH == H)) || (dE && (dE == E || dE == H))) return fail(DGM_ERR_ARG, "outputs alias inputs");
@@ -1391,6 +1453,7 @@ int dgm_apply_curl_dense(dgm_mesh* m, int prec, const float* E, const float* H, 
 int dgm_step_dense(dgm_mesh* m, int prec, float* E, float* H, double dt, int64_t nsteps, hipStream_t s) {
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "the dense variant"))) return rc;
   if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
   if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
   if (nsteps == 0) return DGM_OK;
@@ -1536,6 +1599,7 @@ int dgm_batch_add(dgm_batch* b, dgm_mesh* m, float* E, float* H, double dt, int6
   if (!b || !E || !H || E == H || nsteps < 0 || !std::isfinite(dt) || !id) return fail(DGM_ERR_ARG, "bad batch slot");
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
+  if ((rc = check_equal_orders(m, "a batch slot"))) return rc;
   for (const auto& q : b->active)
     if (q.m == m) return fail(DGM_ERR_ARG, "mesh handle already has an active slot");
   float *TE, *TH;

@@ -42,6 +42,8 @@ SIGNATURES = {
     "dgm_destroy": (_c_i, [_c_p]),
     "dgm_num_elements": (_c_i, [_c_p, _pi64]),
     "dgm_set_order": (_c_i, [_c_p, _c_i]),
+    "dgm_set_orders": (_c_i, [_c_p, _c_i, _c_i]),
+    "dgm_orders": (_c_i, [_c_p, _pi, _pi]),
     "dgm_set_material": (_c_i, [_c_p, _pd, _pd]),
     "dgm_set_check_interval": (_c_i, [_c_p, _c_i64]),
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
@@ -159,7 +161,8 @@ class Mesh:
                                    ctypes.byref(h)))
         self._h = h
         self.K = int(t.shape[0])
-        self.p = None
+        self.p = None   # order of H (and of E unless set_orders gave E one more)
+        self.pE = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -178,11 +181,23 @@ class Mesh:
 
     @property
     def N(self):
+        """Modes per component of H (and of E with equal orders)."""
         return num_modes(self.p)
+
+    @property
+    def NE(self):
+        return num_modes(self.pE)
 
     def set_order(self, p: int):
         _check(load_library().dgm_set_order(self._h, int(p)))
-        self.p = int(p)
+        self.p = self.pE = int(p)
+        return self
+
+    def set_orders(self, pE: int, pH: int):
+        """Mixed orders (Section 2): E of degree pE = pH + 1, H of degree pH (pE == pH is
+        set_order).  E-shaped arrays then have NE modes per component, H-shaped ones N."""
+        _check(load_library().dgm_set_orders(self._h, int(pE), int(pH)))
+        self.p, self.pE = int(pH), int(pE)
         return self
 
     def set_material(self, eps=None, mu=None):
@@ -203,14 +218,18 @@ class Mesh:
         _check(load_library().dgm_set_check_interval(self._h, int(every)))
         return self
 
+    # fields shaped like E (NE modes) and like H (N modes)
+    _E_LIKE = ("E", "dE", "w")
+
     def _field(self, t, name):
         torch = _torch()
         if t is None:
             return None
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise DGMError(f"{name} must be a device tensor")
-        if tuple(t.shape) != (3, self.N, self.K) or not t.is_contiguous():
-            raise DGMError(f"{name} must be contiguous with shape (3, {self.N}, {self.K})")
+        n = self.NE if name in self._E_LIKE else self.N
+        if tuple(t.shape) != (3, n, self.K) or not t.is_contiguous():
+            raise DGMError(f"{name} must be contiguous with shape (3, {n}, {self.K})")
         return t
 
     def _fields(self, **named):
@@ -226,9 +245,11 @@ class Mesh:
                 raise DGMError(f"{n} has dtype {t.dtype}, expected {dt} (all fields must share one dtype)")
         return out, _dtype_code(given[0][1])
 
-    def zeros(self, dtype=None):
+    def zeros(self, dtype=None, field="H"):
+        """Zeroed (3, N, K) array shaped like H (field="E": like E)."""
         torch = _torch()
-        return torch.zeros((3, self.N, self.K), dtype=dtype or torch.float32, device="cuda")
+        n = self.NE if field == "E" else self.N
+        return torch.zeros((3, n, self.K), dtype=dtype or torch.float32, device="cuda")
 
     def apply_curl(self, E=None, H=None, dE=None, dH=None):
         """Returns (dE, dH) = (-M_eps^{-1} C^T H, M_mu^{-1} C E)."""
@@ -238,9 +259,9 @@ class Mesh:
         (E, H, dE, dH), code = self._fields(E=E, H=H, dE=dE if H is not None else None,
                                             dH=dH if E is not None else None)
         if H is not None and dE is None:
-            dE = torch.empty_like(H)
+            dE = torch.empty((3, self.NE, self.K), dtype=H.dtype, device=H.device)
         if E is not None and dH is None:
-            dH = torch.empty_like(E)
+            dH = torch.empty((3, self.N, self.K), dtype=E.dtype, device=E.device)
         _check(load_library().dgm_apply_curl(
             self._h, code, _ptr(E), _ptr(H), _ptr(dE if H is not None else None),
             _ptr(dH if E is not None else None), _stream()))

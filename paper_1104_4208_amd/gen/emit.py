@@ -389,7 +389,7 @@ def _plan_traces(t, g, nw, faces=(0, 1, 2, 3), init=None):
     return [sorted(a) for a in assign], load
 
 
-def _rebalance_intervals(t, g, Lp, bins, nw, cap, rounds=400):
+def _rebalance_intervals(t, tU, g, Lp, bins, nw, cap, rounds=400):
     """The curl (with the own-trace jobs) and the lift run in different barrier
     intervals, so what counts is each interval's most loaded wave.  Starting from the
     total-cost partition, move single (m, k) blocks between waves while that lowers
@@ -407,7 +407,7 @@ def _rebalance_intervals(t, g, Lp, bins, nw, cap, rounds=400):
 
     def objective(bs):
         cs = [parts(b) for b in bs]
-        _, own = _plan_traces(t, g, nw, RECOMPUTED, init=[c[0] for c in cs])
+        _, own = _plan_traces(tU, g, nw, RECOMPUTED, init=[c[0] for c in cs])
         return max(own) + max(c[1] for c in cs)
 
     bins = [list(b) for b in bins]
@@ -448,26 +448,31 @@ def _plan_c2(t, nw):
     return out
 
 
-def plan(p: int, nw: int):
+def plan(p: int, nw: int, pU: int = None, pV: int = None):
     """One output job per wave (volume rows, all three components; unions of (m, k)
     blocks, the unit of the factored lift) and the trace jobs above, balanced over
-    the nw waves with the instruction estimates above."""
-    t = TB.build(p)
-    g, Lp = TB.face_weights(t)
-    tr_w, tr_load = _plan_traces(t, g, nw)
-    blks = [tuple(b) for b in _blocks(t)]
+    the nw waves with the instruction estimates above.  With pU, pV (mixed orders) the
+    differentiated field U has order pU and the updated field V order pV: U's tables
+    drive its own traces and the face-0 conversion, V's tables the trace stage, and
+    the coupling tables the curl and the lift."""
+    pU = p if pU is None else pU
+    pV = p if pV is None else pV
+    tU, tV, tC = TB.build(pU), TB.build(pV), TB.coupling(pU, pV)
+    g, Lp = TB.face_weights(tU)
+    tr_w, tr_load = _plan_traces(tV, g, nw)
+    blks = [tuple(b) for b in _blocks(tC)]
     rows_of = lambda bl: sorted(r for b in bl for r in b)
-    cap = out_rows_cap(p)
-    ob, out_load = _balance(blks, lambda b: _out_job_cost(t, Lp, list(b)),
-                            lambda bl: _out_job_cost(t, Lp, rows_of(bl)), nw,
+    cap = out_rows_cap(max(pU, pV), min(pU, pV))
+    ob, out_load = _balance(blks, lambda b: _out_job_cost(tC, Lp, list(b)),
+                            lambda bl: _out_job_cost(tC, Lp, rows_of(bl)), nw,
                             lambda bl: len(rows_of(bl)) <= cap)
-    ob = _rebalance_intervals(t, g, Lp, ob, nw, cap)
-    out_load = [_out_job_cost(t, Lp, rows_of(bl)) for bl in ob]
+    ob = _rebalance_intervals(tC, tU, g, Lp, ob, nw, cap)
+    out_load = [_out_job_cost(tC, Lp, rows_of(bl)) for bl in ob]
     out_w = [[rows_of(bl)] if bl else [] for bl in ob]
     # the own-trace jobs share a barrier interval with the curl: balance them together
-    curl = [sum(_curl_cost(t, rows) for rows in w) for w in out_w]
-    own_w, own_load = _plan_traces(t, g, nw, RECOMPUTED, init=curl)
-    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load, c2=_plan_c2(t, nw),
+    curl = [sum(_curl_cost(tC, rows) for rows in w) for w in out_w]
+    own_w, own_load = _plan_traces(tU, g, nw, RECOMPUTED, init=curl)
+    return dict(trace=tr_w, trace_load=tr_load, out=out_w, out_load=out_load, c2=_plan_c2(tU, nw),
                 own=own_w, own_load=own_load)
 
 
@@ -688,9 +693,9 @@ def _lift_job(a_, t, Lp, rows, ind):
     """Lifted jumps (from LDS) added to the rates of the wave's rows, face by face,
     then the update V = V_old + sdt * rate of the three components (old values
     fetched before the lift arithmetic when the registers allow)."""
-    N, NF = t.N, t.NF
+    N, NF = t.NV, t.NF
     a_(ind + "{")
-    early = vo_early(t.p)
+    early = vo_early(getattr(t, "launch_p", t.p))
     if early:
         a_(ind + "  // old values of the updated rows")
         for j, b in enumerate(rows):
@@ -761,7 +766,15 @@ def _lift_job(a_, t, Lp, rows, ind):
     a_(ind + "}")
 
 
-def lds_words(p: int) -> int:
+def lds_words(p: int, q: int = None) -> int:
+    """LDS words of one workgroup (with q: a mixed-order kernel of orders p and q, the
+    larger of the two areas)."""
+    if q is not None and q != p:
+        return max(lds_words(p), lds_words(q))
+    return _lds_words(p)
+
+
+def _lds_words(p: int) -> int:
     """LDS words of one workgroup: one area, holding in turn the staged field
     (3N x 64) and the trace jumps (8NF x 64)."""
     t = TB.build(p)
@@ -782,17 +795,17 @@ def vo_early(p: int) -> bool:
     return LAUNCH[p][1] if p in LAUNCH else True
 
 
-def out_rows_cap(p: int) -> int:
+def out_rows_cap(p: int, q: int = None) -> int:
     """Volume rows per output job: OUT_ROWS, or 12 where the launch leaves a lane 128
     registers (four waves per SIMD), so that the rows' accumulators, a factored lift's
     intermediates and a stream group fit without spilling."""
-    waves_per_simd = max(1, waves_for(p) * groups_per_cu(p, 4) // 4)
+    waves_per_simd = max(1, waves_for(p) * groups_per_cu(p, 4, q) // 4)
     return 12 if 512 // waves_per_simd <= 128 else OUT_ROWS
 
 
-def groups_per_cu(p: int, elem_bytes: int) -> int:
+def groups_per_cu(p: int, elem_bytes: int, q: int = None) -> int:
     """Workgroups that share a compute unit (LDS bound, at most 2)."""
-    return max(1, min(2, LDS_BUDGET // (lds_words(p) * elem_bytes)))
+    return max(1, min(2, LDS_BUDGET // (lds_words(p, q) * elem_bytes)))
 
 
 def _stage_parts(t, nw, X, mp):
@@ -1039,46 +1052,47 @@ def _own_trace_stage(a_, t, g, pl, nw):
         a_("  }")
 
 
-def _phase_body(a_, t, g, Lp, pl, nw):
+def _phase_body(a_, tU, tV, tC, g, Lp, pl, nw):
     """Stages of one phase (shared by the single-mesh and the batched kernel), one
     LDS area used in turn: A stage U (derivative frame), B curl of the wave's rows
     into registers, C jumps of the traces of U, D lift + update of V, and if Tout:
     E the updated rows (kept in registers) into LDS in the derivative frame of V,
-    F its traces to Tout."""
-    N = t.N
+    F its traces to Tout.  tU: tables of U's order (staging, own traces, jumps, face-0
+    conversion), tV: of V's order (its traces), tC: the coupling (curl and lift)."""
+    N = tV.N
     J = max(len(rows) for w in pl["out"] for rows in w) if any(pl["out"]) else 0
     for k in range(3):
         for j0 in range(0, J, 16):
             a_("  R " + ", ".join(f"acc{k}_{j} = R(0)" for j in range(j0, min(J, j0 + 16))) + ";")
     a_("  // A: the tile's own field in the derivative frame, w = M S, into LDS")
-    _stage_field(a_, t, nw, "U", "MU")
+    _stage_field(a_, tU, nw, "U", "MU")
     a_("  __syncthreads();")
     a_("  // B: curl of the wave's rows (all components) into registers")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for rows in pl["out"][w]:
             a_(f"    // volume modes {', '.join(map(str, rows))}")
-            _curl_job(a_, t, rows, "    ")
+            _curl_job(a_, tC, rows, "    ")
         a_("  }")
     a_("  // T: own traces of U on every face into LDS (recomputed faces from the staged")
     a_("  // field, the others from Tin)")
-    _own_trace_stage(a_, t, g, pl, nw)
+    _own_trace_stage(a_, tU, g, pl, nw)
     a_("  __syncthreads();")
     a_("  // C: jumps of the traces of U (neighbour from LDS in the tile, else from Tin)")
     a_("  {")
-    for l in _jump_lines(t, nw):
+    for l in _jump_lines(tU, nw):
         a_("    " + l)
     a_("  }")
     a_("  __syncthreads();")
-    _stab_stage(a_, t, nw)
+    _stab_stage(a_, tU, nw)
     a_("  // C2: face 0's jumps from psi to the collapsed basis of the lift factors, in place")
-    _c2_stage(a_, t, pl, nw)
+    _c2_stage(a_, tU, pl, nw)
     a_("  __syncthreads();")
     a_("  // D: lifted jumps and the component-separable update of V")
     for w in range(nw):
         a_(f"  if (wave == {w}) {{")
         for rows in pl["out"][w]:
-            _lift_job(a_, t, Lp, rows, "    ")
+            _lift_job(a_, tC, Lp, rows, "    ")
         a_("  }")
     FLOPS_NO_TRACE = FLOPS[0]
     a_("  if (Tout == nullptr) return;")
@@ -1100,21 +1114,27 @@ def _phase_body(a_, t, g, Lp, pl, nw):
     a_("  __syncthreads();")
     a_("  // F: its traces for the next phase")
     before_f = FLOPS[0]
-    _trace_stage(a_, t, g, pl, nw)
+    _trace_stage(a_, tV, g, pl, nw)
     return dict(no_traces=FLOPS_NO_TRACE, with_traces=FLOPS[0], trace_stage=FLOPS[0] - before_f)
 
 
-def _kernel_setup(p):
-    t = TB.build(p)
-    g, Lp = TB.face_weights(t)
-    nw = waves_for(p)
-    return t, g, Lp, nw, plan(p, nw)
+def _kernel_setup(p, pU=None, pV=None):
+    """Tables and plan of the kernel of order p, or of the mixed-order kernel
+    differentiating order pU and updating order pV (launched as order max(pU, pV))."""
+    pU = p if pU is None else pU
+    pV = p if pV is None else pV
+    tU, tV, tC = TB.build(pU), TB.build(pV), TB.coupling(pU, pV)
+    if pU != pV:
+        tC.launch_p = max(pU, pV)
+    g, Lp = TB.face_weights(tU)
+    nw = waves_for(max(pU, pV))
+    return tU, tV, tC, g, Lp, nw, plan(p, nw, pU, pV)
 
 
-def _launch_bounds(p, nw):
+def _launch_bounds(p, nw, q=None):
     """Threads per workgroup and minimum waves per SIMD (from the LDS-bound number
     of workgroups per CU at FP32), which caps the registers per lane."""
-    return f"__launch_bounds__({nw * LANES}, {max(1, nw * groups_per_cu(p, 4) // 4)})"
+    return f"__launch_bounds__({nw * LANES}, {max(1, nw * groups_per_cu(p, 4, q) // 4)})"
 
 
 def _tile_prologue(a_):
@@ -1134,43 +1154,54 @@ def _elem_prologue(a_):
     a_("  const size_t Ks = (size_t)K;")
 
 
-def _header(a_, p, t, nw, pl, what):
+def _header(a_, p, t, nw, pl, what, q=None):
     FS, ES = trace_strides(t.NF)
     a_(f"// Generated by gen/emit.py for order p = {p}: N = {t.N} volume modes, NF = {t.NF} face modes; {what}.")
-    a_(f"// {nw} waves share {LANES} elements (one per lane), {lds_words(p)} LDS words; trace buffer")
+    a_(f"// {nw} waves share {LANES} elements (one per lane), {lds_words(p, q)} LDS words; trace buffer")
     a_(f"// strides: face {FS}, element {ES}; per-wave cost of the trace jobs {pl['trace_load']},")
     a_(f"// of the update jobs {pl['out_load']}.")
     a_(f"static_assert(trace_face_stride({t.NF}) == {FS} && trace_elem_stride({t.NF}) == {ES}, \"trace layout\");")
 
 
-def emit_phase(p: int) -> str:
-    """Single-mesh phase kernel of order p."""
-    t, g, Lp, nw, pl = _kernel_setup(p)
+def emit_phase(p: int, pU: int = None, pV: int = None, name: str = None) -> str:
+    """Single-mesh phase kernel of order p, or (pU, pV) the mixed-order kernel that
+    differentiates a field of order pU and updates one of order pV."""
+    tU, tV, tC, g, Lp, nw, pl = _kernel_setup(p, pU, pV)
+    mixed = tU.p != tV.p
+    q = min(tU.p, tV.p) if mixed else None
+    kp = max(tU.p, tV.p)
+    name = name or f"dgm_phase_p{p}"
     L = []
     a_ = L.append
-    _header(a_, p, t, nw, pl, "single-mesh phase")
+    _header(a_, kp, tU, nw, pl, f"single-mesh phase, U of order {tU.p}, V of order {tV.p}" if mixed
+            else "single-mesh phase", q)
+    if mixed:
+        a_(f"static_assert(trace_face_stride({tV.NF}) == {trace_strides(tV.NF)[0]}, \"trace layout of V\");")
     a_("// ST: field loads and stores and trace stores carry the nontemporal hint (launch.h)")
     a_("// STAB: stabilised central flux with face unknowns HF (Section 2.1)")
     a_("template <typename R, bool ST, bool STAB>")
-    a_(f"__global__ void {_launch_bounds(p, nw)} dgm_phase_p{p}(const R* __restrict__ U, R* __restrict__ V,")
+    a_(f"__global__ void {_launch_bounds(kp, nw, q)} {name}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
     a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K,")
     a_("    R* __restrict__ HF, const R* __restrict__ SC, R fdt)")
     a_("{")
-    a_(f"  __shared__ R wl[{lds_words(p)}];")
+    if mixed:
+        a_("  static_assert(!STAB, \"the stabilised flux is built for equal orders\");")
+    a_(f"  __shared__ R wl[{lds_words(kp, q)}];")
     _tile_prologue(a_)
     _elem_prologue(a_)
     FLOPS[0] = 0
-    cnt = _phase_body(a_, t, g, Lp, pl, nw)
+    cnt = _phase_body(a_, tU, tV, tC, g, Lp, pl, nw)
     # the recomputed faces' trace jobs in stage F run only in tiles with an off-tile
     # neighbour across that face: their share is reported apart
     FLOPS[0] = 0
     for w in range(nw):
         for (f, k, rows) in pl["trace"][w]:
             if f in RECOMPUTED:
-                _trace_job(lambda x: None, t, g, f, k, rows, "", sink=lambda *a: None)
+                _trace_job(lambda x: None, tV, g, f, k, rows, "", sink=lambda *a: None)
     cnt["trace_stage_recomputed_faces"] = FLOPS[0]
-    OPCOUNT[p] = dict(cnt, N=t.N, NF=t.NF, waves=nw)
+    if not mixed:
+        OPCOUNT[p] = dict(cnt, N=tU.N, NF=tU.NF, waves=nw)
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -1178,7 +1209,7 @@ def emit_phase(p: int) -> str:
 def emit_trace(p: int) -> str:
     """Trace kernel of order p: the traces of one field (the first phase of a run
     and the rate operator need them before any phase has written them)."""
-    t, g, Lp, nw, pl = _kernel_setup(p)
+    t, _, _, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
     _header(a_, p, t, nw, pl, "trace kernel")
@@ -1199,7 +1230,7 @@ def emit_trace(p: int) -> str:
 
 def emit_batch(p: int) -> str:
     """Batched multi-mesh phase kernel of order p (FP32)."""
-    t, g, Lp, nw, pl = _kernel_setup(p)
+    t, _, _, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
     _header(a_, p, t, nw, pl, "batched phase")
@@ -1234,7 +1265,7 @@ def emit_batch(p: int) -> str:
     a_("  const R fdt = R(0);")
     a_("  const int tile = bid - tile0[lo];")
     _elem_prologue(a_)
-    _phase_body(a_, t, g, Lp, pl, nw)
+    _phase_body(a_, t, t, t, g, Lp, pl, nw)
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -1304,6 +1335,8 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               "  return hipGetLastError();",
               "}"]
         units.append(_write_if_changed(os.path.join(outdir, f"batch_p{p}.hip"), "\n".join(tb) + "\n"))
+        if p + 1 in orders:
+            units.append(_emit_mixed(outdir, p))
     fr = TB.frame()
     A, Ai = fr["A"], fr["Ainv"]
     lines = ["// Generated by gen/emit.py: derivative frame and compiled orders.",
@@ -1324,6 +1357,10 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     lines += decl
     for p in orders:
         lines.append(f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a);")
+        if p + 1 in orders:
+            lines.append(f"hipError_t dgm_launch_mix_p{p}_f32(const PhaseArgs<float>& a, int dir);")
+            if p + 1 <= F64_MAX_ORDER:
+                lines.append(f"hipError_t dgm_launch_mix_p{p}_f64(const PhaseArgs<double>& a, int dir);")
     lines += launcher_tables(orders)
     _write_if_changed(os.path.join(outdir, "frame.inc"), "\n".join(lines) + "\n")
     _write_if_changed(os.path.join(outdir, "tables.inc"), emit_host_tables(orders))
@@ -1338,6 +1375,36 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
     return units
 
 
+def _emit_mixed(outdir, p):
+    """Mixed-order kernels of the pair (E of order p + 1, H of order p): dgm_phase_eh_p{p}
+    updates H from E, dgm_phase_he_p{p} updates E from H; one launcher picks by direction."""
+    nw = waves_for(p + 1)
+    src = (emit_phase(p, p + 1, p, f"dgm_phase_eh_p{p}") + emit_phase(p, p, p + 1, f"dgm_phase_he_p{p}"))
+    _write_if_changed(os.path.join(outdir, f"mix_p{p}.inc"), src)
+    args = "a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt"
+    tu = [f"// Generated by gen/emit.py: mixed-order kernels (E of order {p + 1}, H of order {p}) and launcher.",
+          "#include <hip/hip_runtime.h>",
+          '#include "../launch.h"',
+          f'#include "mix_p{p}.inc"',
+          "// dir 0: H update from E (U = E of order p + 1, V = H); 1: E update from H",
+          "template <typename R>",
+          f"static hipError_t launch_mix_p{p}(const PhaseArgs<R>& a, int dir) {{",
+          "  if (dir == 0 && a.streaming)",
+          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          "  else if (dir == 0)",
+          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          "  else if (a.streaming)",
+          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          "  else",
+          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          "  return hipGetLastError();",
+          "}",
+          f"hipError_t dgm_launch_mix_p{p}_f32(const PhaseArgs<float>& a, int dir) {{ return launch_mix_p{p}<float>(a, dir); }}"]
+    if p + 1 <= F64_MAX_ORDER:
+        tu.append(f"hipError_t dgm_launch_mix_p{p}_f64(const PhaseArgs<double>& a, int dir) {{ return launch_mix_p{p}<double>(a, dir); }}")
+    return _write_if_changed(os.path.join(outdir, f"mix_p{p}.hip"), "\n".join(tu) + "\n")
+
+
 def launcher_tables(orders):
     """Launcher tables indexed by order: entry p is the launcher of order p, nullptr
     where order p was not built (or is not instantiated for that precision).  Every
@@ -1350,7 +1417,11 @@ def launcher_tables(orders):
         return f"static {decl.format(n=top + 1)} = {{{ents}}};"
 
     f64 = lambda p: p <= F64_MAX_ORDER
+    mix = lambda p: p + 1 in orders
     return [
+        table("hipError_t (*const kMixF32[{n}])(const PhaseArgs<float>&, int)", "dgm_launch_mix_p{p}_f32", mix),
+        table("hipError_t (*const kMixF64[{n}])(const PhaseArgs<double>&, int)", "dgm_launch_mix_p{p}_f64",
+              lambda p: mix(p) and p + 1 <= F64_MAX_ORDER),
         table("hipError_t (*const kTraceF32[{n}])(const TraceArgs<float>&)", "dgm_launch_trace_p{p}_f32", lambda p: True),
         table("hipError_t (*const kTraceF64[{n}])(const TraceArgs<double>&)", "dgm_launch_trace_p{p}_f64", f64),
         table("hipError_t (*const kPhaseF32[{n}])(const PhaseArgs<float>&)", "dgm_launch_phase_p{p}_f32", lambda p: True),

@@ -57,6 +57,40 @@ class Tables:
         self.fmodes = B.face_modes(p)
         self.N = len(self.modes)
         self.NF = len(self.fmodes)
+        self.NV = self.N  # rows of the updated field (differs only in a mixed-order coupling)
+
+
+class Coupling:
+    """Operators of a phase between fields of different orders (Section 2: E of degree
+    p + 1, H of degree p).  U (the differentiated field) has order pU, V (the updated one)
+    order pV.  Because the mode orders are hierarchical (degree-major), every operator is
+    a block of the higher order's exact table: the curl maps the N_U modes of U into the
+    N_V rows of V (D[:N_V, :N_U]), the lift maps U's NF_U face modes into V's rows
+    (T[:NF_U, :N_V]^T; a degree-pU trace has no component on higher face modes), and the
+    collapsed factors are sliced the same way.  Attributes mirror Tables: N = N_U (the
+    staged field's modes), NV = N_V, NF = NF_U, modes / p of V (its (m, k) blocks),
+    fmodes of U."""
+
+    def __init__(self, pU, pV):
+        t = build(max(pU, pV))
+        u, v = build(pU), build(pV)
+        self.p, self.pU = pV, pU
+        self.modes, self.fmodes = v.modes, u.fmodes
+        self.N, self.NV, self.NF = u.N, v.N, u.NF
+        self.D = [D[:v.N, :u.N] for D in t.D]
+        self.T = [T[:u.NF, :v.N] for T in t.T]
+        fac = t.fac
+        self.fac = dict(X=fac["X"], A3=fac["A3"][:, :v.N], A0=fac["A0"][:, :v.N], B=fac["B"][:u.NF],
+                        C=fac["C"][:u.NF, :u.NF])
+        self.tang, self.normal, self.L, self.frame = t.tang, t.normal, t.L, t.frame
+        self.mixed = pU != pV
+
+
+@functools.lru_cache(maxsize=None)
+def coupling(pU: int, pV: int):
+    """Tables of the phase differentiating order pU and updating order pV (the order's own
+    Tables when they are equal)."""
+    return build(pU) if pU == pV else Coupling(pU, pV)
 
 
 def _clean(M, what):

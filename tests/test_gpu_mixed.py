@@ -1,0 +1,182 @@
+"""Mixed orders (E of degree p+1, H of degree p; Section 2): the HIP path against the
+oracle's MixedSolver, element by element, through the C-ABI.  Tolerances as for equal
+orders: FP64 1e-10, FP32 1e-5 relative to the largest value, runs in the energy norm."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import frames, patch, rel_err, sort_tets
+from oracle.mixed import MixedSolver
+from paper_1104_4208_amd.gen.basis import volume_modes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1104_4208_amd as P  # noqa: E402
+
+
+class MixedPair:
+    """The oracle's mixed solver on the library's elements, with the representation
+    changes of both fields (physical (K,N,3) <-> covariant (3,N,K), mode orders)."""
+
+    def __init__(self, verts, tets, pE, pH, eps=None, mu=None):
+        self.s = MixedSolver(oracle.build_mesh(np.asarray(verts, float), sort_tets(tets)), pE, pH, eps, mu)
+        self.F = frames(verts, tets)
+        self.pm = {}
+        for p in (pE, pH):
+            idx = {m: r for r, m in enumerate(oracle.mode_list(p))}
+            pm = np.array([idx[m] for m in volume_modes(p)])
+            ipm = np.empty_like(pm)
+            ipm[pm] = np.arange(len(pm))
+            self.pm[p] = (pm, ipm)
+        self.pE, self.pH = pE, pH
+
+    def to_cov(self, phys, p):
+        return np.einsum("kji,kmj->imk", self.F, phys)[:, self.pm[p][0], :]
+
+    def to_phys(self, cov, p):
+        c = np.asarray(cov, float)[:, self.pm[p][1], :]
+        return np.einsum("kji,jmk->kmi", np.linalg.inv(self.F), c)
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+MESHES = {
+    "one": lambda rng: synth.single_tet(np.array([[0.1, 0, 0], [1, 0.2, 0], [0, 1.1, 0.1], [0.2, 0.1, 0.9]])),
+    "two_unsorted": lambda rng: synth.two_tets(rng),
+    "cube1": lambda rng: synth.kuhn_mesh(1),
+    "jit2": lambda rng: synth.kuhn_mesh(2, 0.1, rng),
+    "jit3_ragged": lambda rng: synth.kuhn_mesh(3, 0.1, rng),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("pH", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("mesh", list(MESHES))
+def test_mixed_apply_curl_parity(mesh, pH, dtype):
+    pE = pH + 1
+    if dtype == "f64" and pE > P.max_order(P.DGM_F64):
+        pytest.skip("order not compiled for FP64")
+    if pH >= 4 and mesh == "jit3_ragged":
+        pytest.skip("covered at lower orders; keeps the oracle fast")
+    rng = np.random.default_rng(500 + pH)
+    verts, tets = MESHES[mesh](rng)
+    K = tets.shape[0]
+    eps, mu = rng.uniform(1, 4, K), rng.uniform(1, 2, K)
+    pr = MixedPair(verts, tets, pE, pH, eps, mu)
+    E = rng.standard_normal((K, pr.s.NE, 3))
+    H = rng.standard_normal((K, pr.s.NH, 3))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    m = P.Mesh(verts, tets).set_orders(pE, pH).set_material(eps, mu)
+    dE, dH = m.apply_curl(dev(pr.to_cov(E, pE), tdt), dev(pr.to_cov(H, pH), tdt))
+    ee = rel_err(host(dE), pr.to_cov(pr.s.rhs_e(H), pE))
+    eh = rel_err(host(dH), pr.to_cov(pr.s.rhs_h(E), pH))
+    print(f"mixed ({pE},{pH}) {mesh} {dtype}: dE {ee:.2e} dH {eh:.2e}")
+    assert ee < tol and eh < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_mixed_run_against_oracle(dtype, tol):
+    """TE101 on the jittered 48-tet cube with (pE, pH) = (3, 2), eps in {1, 4}: 80
+    leapfrog steps against the oracle's, and the leapfrog invariant."""
+    rng = np.random.default_rng(41)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K = tets.shape[0]
+    eps = rng.choice([1.0, 4.0], size=K)
+    pr = MixedPair(verts, tets, 3, 2, eps, None)
+    s = pr.s
+    E = s.project(synth.te101().E, "E")
+    H = np.zeros((K, s.NH, 3))
+    dt = 1.0 / math.sqrt(s.spectral_radius(40, synth.splitmix64(41, H.size)))
+    m = P.Mesh(verts, tets).set_orders(3, 2).set_material(eps, None)
+    Eg, Hg = dev(pr.to_cov(E, 3), dtype), dev(pr.to_cov(H, 2), dtype)
+    _, Q0 = m.energy(Eg, Hg, dt=dt)
+    Q0o = s.leapfrog_invariant(E, H, dt)
+    assert abs(Q0 - Q0o) < (1e-10 if dtype == torch.float64 else 1e-6) * Q0o
+    worst, drift = 0.0, 0.0
+    for _ in range(8):
+        m.step(Eg, Hg, dt, 10)
+        E, H = s.step(E, H, dt, 10)
+        worst = max(worst, s.rel_error(pr.to_phys(host(Eg), 3), pr.to_phys(host(Hg), 2), E, H))
+        _, Q = m.energy(Eg, Hg, dt=dt)
+        drift = max(drift, abs(Q - Q0) / Q0)
+    print(f"mixed run {dtype}: worst energy-norm error {worst:.2e}, Q drift {drift:.2e}")
+    assert worst < tol
+    assert drift < (1e-12 if dtype == torch.float64 else 1e-6)
+
+
+def test_mixed_estimate_dt_and_spectrum():
+    """The power iteration approaches the largest eigenvalue of the mixed operator from
+    below (within 1e-3 of the oracle's assembled value after 200 iterations)."""
+    verts, tets = synth.kuhn_mesh(1)
+    pr = MixedPair(verts, tets, 3, 2)
+    Ah, Ae = pr.s.assemble()
+    rho = float(np.linalg.eigvals(-(Ah @ Ae)).real.max())
+    m = P.Mesh(verts, tets).set_orders(3, 2)
+    dt, est = m.estimate_dt(cfl=0.5, iters=200, seed=7)
+    print(f"mixed rho: library {est:.8e}, assembled oracle {rho:.8e}")
+    assert rho * (1 - 1e-3) < est < rho * (1 + 1e-12)
+
+
+def test_mixed_full_size_sampled():
+    """(pE, pH) = (5, 4) on the 16^3 x 6 jittered cube, FP32: one application, sampled
+    elements against the oracle on their patch meshes; and a step through the
+    allocation-free entry point equals dgm_step bitwise."""
+    rng = np.random.default_rng(54)
+    n, pE, pH = 16, 5, 4
+    verts, tets = synth.kuhn_mesh(n, 0.1, rng)
+    K = tets.shape[0]
+    eps = rng.choice([1.0, 4.0], size=K)
+    m = P.Mesh(verts, tets).set_orders(pE, pH).set_material(eps, None)
+    Ecov = rng.standard_normal((3, P.num_modes(pE), K)).astype(np.float32)
+    Hcov = rng.standard_normal((3, P.num_modes(pH), K)).astype(np.float32)
+    dE, dH = m.apply_curl(dev(Ecov, torch.float32), dev(Hcov, torch.float32))
+    dE, dH = host(dE), host(dH)
+    centers = np.unique(np.concatenate([rng.integers(0, K, 8), [0, K - 1]]))
+    keep, ptets, pos = patch(tets, centers)
+    pr = MixedPair(verts, ptets, pE, pH, eps[keep], None)
+    ref_dE = pr.to_cov(pr.s.rhs_e(pr.to_phys(Hcov[:, :, keep].astype(np.float64), pH)), pE)[:, :, pos]
+    ref_dH = pr.to_cov(pr.s.rhs_h(pr.to_phys(Ecov[:, :, keep].astype(np.float64), pE)), pH)[:, :, pos]
+    ee, eh = rel_err(dE[:, :, centers], ref_dE), rel_err(dH[:, :, centers], ref_dH)
+    print(f"mixed 16^3 ({pE},{pH}) sampled {len(centers)}: dE {ee:.2e} dH {eh:.2e}")
+    assert ee < 1e-5 and eh < 1e-5
+    # allocation-free step on a small mixed mesh, bitwise against dgm_step
+    v2, t2 = synth.kuhn_mesh(4, 0.1, rng)
+    m2 = P.Mesh(v2, t2).set_orders(3, 2)
+    E0 = dev(rng.standard_normal((3, P.num_modes(3), t2.shape[0])), torch.float32)
+    H0 = dev(rng.standard_normal((3, P.num_modes(2), t2.shape[0])), torch.float32)
+    Ea, Ha, Eb, Hb = E0.clone(), H0.clone(), E0.clone(), H0.clone()
+    m2.step(Ea, Ha, 1e-3, 7)
+    m2.step_noalloc(Eb, Hb, 1e-3, 7)
+    torch.cuda.synchronize()
+    assert torch.equal(Ea, Eb) and torch.equal(Ha, Hb)
+
+
+def test_mixed_orders_rejected_where_unsupported():
+    verts, tets = synth.kuhn_mesh(1)
+    m = P.Mesh(verts, tets)
+    with pytest.raises(P.DGMError, match="DGM_ERR_ARG"):
+        m.set_orders(5, 3)
+    m.set_orders(3, 2).set_stab_alpha(1.0)
+    E = m.zeros(torch.float32, field="E")
+    H = m.zeros(torch.float32)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.energy_stab(E, H, m.face_zeros(torch.float32))
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.apply_curl_dense(E, H)
+    b = P.Batch(chunk=2)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        b.add(m, E, H, 1e-3, 2)
+    with pytest.raises(P.DGMError):
+        m.step(H.clone(), H, 1e-3, 1)  # E with H's shape
