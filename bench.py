@@ -23,7 +23,7 @@ without packed FP32.  roofline.traffic and alu.valu_issue_frac: from the committ
 counter summary when it was taken on the current kernel source.  The run then
 continues to the configuration's 500 steps for the drift of the leapfrog
 invariant.  stabilized_flux: the stabilised central flux (Section 2.1) on the same
-mesh.  dense_variant: the p = 8 matrix-core comparison.  serving: the 256-request
+mesh; mixed_orders: E of degree 7, H of degree 6 (Section 2) on the same mesh.  dense_variant: the p = 8 matrix-core comparison.  serving: the 256-request
 trace, batched against sequential.  cpu_baseline: the FP64 oracle timed on a
 bounded sample of the same workload (smaller cube, same order and recipe); the
 same leg (the only code here that runs the oracle) reports under "accuracy" the
@@ -92,7 +92,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-nmax", type=int, default=24)
     ap.add_argument("--no-stab", action="store_true", help="skip the stabilised-flux leg")
-    ap.add_argument("--stab-steps", type=int, default=100)
+    ap.add_argument("--stab-steps", type=int, default=100, help="steps of the stabilised and mixed-order legs")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-order leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run three plain device copies of this many MiB (scale reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -260,6 +261,51 @@ def stab_leg(w, d, E0, steps: int):
             "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps + 8}
 
 
+def mixed_leg(w, d, steps: int, pE: int = 7, pH: int = 6):
+    """Mixed orders (Section 2: E of degree pE = pH + 1, H of degree pH) on the benchmark
+    mesh, FP32: time per step, DOF-updates/s over 3 (N_E + N_H) K unknowns, and the HBM
+    fraction of its algorithmic traffic 36 (N_E + N_H) + 80 bytes per element-step (each
+    phase reads the differentiated field, reads and writes the updated one, 24 B of metric
+    and 16 B of codes)."""
+    import torch
+
+    import paper_1104_4208_amd as P
+
+    from paper_1104_4208_amd.project import project_covariant
+
+    K = d["tets"].shape[0]
+    NE, NH = P.num_modes(pE), P.num_modes(pH)
+    m = P.Mesh(d["verts"], d["tets"]).set_orders(pE, pH).set_material(d["eps"], d["mu"])
+    dt, rho = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
+    E = torch.tensor(np.ascontiguousarray(project_covariant(d["verts"], d["tets"], pE, d["field"].E)),
+                     dtype=torch.float32, device="cuda")
+    H = m.zeros(torch.float32)
+    _, Q0 = m.energy(E, H, dt=dt)
+    m.step(E, H, dt, 5)
+
+    def timed(nsteps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        m.step(E, H, dt, nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one = min(timed(1) for _ in range(3))
+    t = timed(steps)
+    _, Q1 = m.energy(E, H, dt=dt)
+    step_s = (t - one) / (steps - 1)
+    bpe = 36 * (NE + NH) + 80
+    del E, H, m
+    torch.cuda.empty_cache()
+    return {"workload": f"pec_cube_cavity_kuhn32_mixed_pE{pE}_pH{pH}_fp32", "pE": pE, "pH": pH, "dt": dt,
+            "rho": rho, "steps": steps, "ms_per_step": step_s * 1e3,
+            "dof_updates_per_s": 3 * (NE + NH) * K / step_s, "algorithmic_bytes_per_element_step": bpe,
+            "hbm_frac": K * bpe / step_s / (HBM_PEAK_GBS * 1e9), "Q_rel_drift": abs(Q1 - Q0) / Q0,
+            "steps_total": steps + 8}
+
+
 def dense_comparison(steps: int):
     """p = 8 workload (24^3 x 6 = 82,944 tets, random modal data, seed 4): the FP32
     sparse path against the dense matrix-core variant with BF16 and FP16 operands.
@@ -420,6 +466,8 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_stab:
         out["stabilized_flux"] = stab_leg(w, d, E0, a.stab_steps)
+    if not a.no_mixed:
+        out["mixed_orders"] = mixed_leg(w, d, a.stab_steps)
     if not a.no_dense:
         out["dense_variant"] = dense_comparison(a.dense_steps)
     if not a.no_serve:
