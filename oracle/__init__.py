@@ -17,6 +17,9 @@ Contents
              per-face tangential unknowns, their update from the tangential
              jump of E, the extra E-equation term, energies, assembly.
   mixed   -- mixed orders, E of degree p+1 and H of degree p (Section 2).
+  varcoef -- material varying inside the elements through the approximate mass
+             inverse of Section 3.3.2 (reverse integration, division by the
+             material at the points, integration).
 
 Pins (tests/test_oracle.py) tie each function to something other than
 itself: closed-form norms, orthogonality, integration by parts, exact
@@ -28,7 +31,9 @@ null-space dimension in closed form, cavity eigenvalues kept and spurious
 ones removed, reduction to the central flux, exact leapfrog invariant;
 tests/test_oracle_mixed.py for mixed orders: skew-symmetry, exact curls of
 global polynomials, exact invariant, no spurious mode below the first cavity
-mode, TE101 convergence).
+mode, TE101 convergence; tests/test_oracle_varcoef.py for the approximate mass
+inverse: exact for constant material, symmetric positive definite, second-order
+agreement with the exact inverse, skew in its own inner product, exact invariant).
 
 Parity unpinned: the paper's own experiments (the spherical resonator of
 Section 2.2 and the timings of Section 3.5) cannot be reproduced here: the
@@ -38,4 +43,5 @@ from .basis import eval_basis, mode_list, num_modes, tet_quadrature, triangle_qu
 from .dg import Mesh, Solver, build_mesh  # noqa: F401
 from .stab import StabilizedSolver  # noqa: F401
 from .mixed import MixedSolver  # noqa: F401
+from .varcoef import VarMaterialSolver  # noqa: F401
 from .jacobi import djacobi, gauss_jacobi, jacobi  # noqa: F401
