@@ -99,6 +99,28 @@ int dgm_set_order(dgm_mesh* mesh, int p);
  * DGM_ERR_HIP. */
 int dgm_set_material(dgm_mesh* mesh, const double* eps, const double* mu);
 
+/* Permittivity and permeability that vary linearly inside every element (Section
+ * 3.3.2): host arrays (K,4) row-major, the values at the element's four vertices in
+ * the order the element was given to dgm_create_mesh (each > 0; NULL means 1), so a
+ * field continuous across faces or one that jumps between elements are both
+ * possible.  The mass matrix of such a material is no longer the flat one; its
+ * inverse is replaced by the approximate inverse of Section 3.3.2: the rate's point
+ * values at the collapsed Gauss rule with p + 1 points per direction (the reverse of
+ * numerical integration), divided by the material at the points, integrated back,
+ *     (P r)_a = sum_x w_x phi_a(x) (sum_b phi_b(x) r_b) / m(x),
+ * applied to every component (sum factorisation, O(p^4) per element: one generated
+ * kernel per order).  The rule is laid on the element's reference map with vertices
+ * sorted by global id.  P is symmetric positive definite and exact for constant
+ * material (then this reproduces dgm_set_material up to rounding).  dgm_apply_curl,
+ * dgm_step, dgm_step_probe (E mapped by the unit-material factors), dgm_energy
+ * (W and Q with M~ = P^{-1}, one preconditioned conjugate-gradient solve per field,
+ * in FP64 where the orders have FP64 kernels) and dgm_estimate_dt (in the M~ inner
+ * product) use it, with equal or mixed orders; the stabilised flux, the dense variant,
+ * batch slots and dgm_step_noalloc return DGM_ERR_STATE until dgm_set_material is
+ * called again.  Every value is checked before anything changes.  Errors:
+ * DGM_ERR_MATERIAL, DGM_ERR_OOM, DGM_ERR_HIP. */
+int dgm_set_material_linear(dgm_mesh* mesh, const double* eps, const double* mu);
+
 /* Semi-discrete right-hand side (Section 2.1, eq. semidiscrete):
  *     dE = -M_eps^{-1} C^T H  (= eps^{-1} curl_h H),
  *     dH =  M_mu^{-1} C E     (= -mu^{-1} curl_h E),

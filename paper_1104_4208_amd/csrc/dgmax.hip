@@ -21,6 +21,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dgmax.h"
@@ -220,6 +221,49 @@ __global__ void splitmix_fill_kernel(R* __restrict__ X, size_t n, unsigned long 
   }
 }
 
+// Conjugate gradients for the approximate mass matrix of a material that varies inside
+// the elements (Section 3.3.2).  The scalars stay in device memory, so an iteration
+// makes no host round trip: rz[0] = r.z, pt = p.t.
+// x += alpha p, r -= alpha t, alpha = r.z / p.t (zero once the residual is zero)
+template <typename R>
+__global__ void cg_xr_kernel(R* __restrict__ x, R* __restrict__ r, const R* __restrict__ p, const R* __restrict__ t,
+                             size_t n, const double* __restrict__ rz, const double* __restrict__ pt) {
+  const double alpha = *pt != 0.0 ? *rz / *pt : 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    x[i] = (R)((double)x[i] + alpha * (double)p[i]);
+    r[i] = (R)((double)r[i] - alpha * (double)t[i]);
+  }
+}
+
+// t = mbar_e r with mbar_e the mean of the element's four vertex values (the
+// approximate inverse is close to 1 / mbar_e, so this is the preconditioner; also the
+// start value of the solution).  Field layout (3,N,K): element e = i mod K.
+template <typename R>
+__global__ void cg_precond_kernel(R* __restrict__ t, const R* __restrict__ r, const R* __restrict__ mat, size_t n,
+                                  int K) {
+  const size_t Ks = (size_t)K;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t e = i % Ks;
+    const double mbar = 0.25 * ((double)mat[e] + (double)mat[Ks + e] + (double)mat[2 * Ks + e] + (double)mat[3 * Ks + e]);
+    t[i] = (R)(mbar * (double)r[i]);
+  }
+}
+
+// p = t + beta p, beta = rz_new / rz_old
+template <typename R>
+__global__ void cg_p_kernel(R* __restrict__ p, const R* __restrict__ t, size_t n, const double* __restrict__ rz_new,
+                            const double* __restrict__ rz_old) {
+  const double beta = *rz_old != 0.0 ? *rz_new / *rz_old : 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (R)((double)t[i] + beta * (double)p[i]);
+}
+
+template <typename A, typename B>
+__global__ void cast_kernel(B* __restrict__ out, const A* __restrict__ in, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (B)in[i];
+}
+
 template <typename R>
 __global__ void scale_kernel(R* __restrict__ X, size_t n, const double* __restrict__ d) {
   const double r = sqrt(*d);
@@ -237,6 +281,7 @@ struct dgm_mesh {
   std::vector<double> F;   // (K,9) row-major 3x3, columns v1-v0, v2-v0, v3-v0 (sorted vertices)
   std::vector<double> J;   // signed det F
   std::vector<int> nbr;    // (4,K)
+  std::vector<unsigned char> perm;  // (K,4): caller's position of each sorted vertex
   // device: one block (d_geom) holds the neighbour codes and every per-element factor;
   // the pointers below point into it and are never freed on their own
   void* d_geom = nullptr;
@@ -264,6 +309,13 @@ struct dgm_mesh {
   float* d_SC32 = nullptr;
   double* d_SC64 = nullptr;
   double* d_WF = nullptr;
+  // material linear on every element (dgm_set_material_linear): the mass inverse is the
+  // approximate one of Section 3.3.2, the metrics above are those of unit material, and
+  // d_var holds eps then mu at the sorted vertices, (4,K) each, in FP32 then FP64
+  bool varmat = false;
+  void* d_var = nullptr;
+  float* d_var32[2] = {nullptr, nullptr};
+  double* d_var64[2] = {nullptr, nullptr};
   // dense matrix-core variant: operators per precision (BF16, FP16) and jump scratch
   DenseOps* dense[2] = {nullptr, nullptr};
   float* d_jump = nullptr;
@@ -434,6 +486,14 @@ hipError_t mix(const PhaseArgs<float>& a, int p, int dir) { return kMixF32[p](a,
 hipError_t mix(const PhaseArgs<double>& a, int p, int dir) { return kMixF64[p](a, dir); }
 hipError_t trace(const TraceArgs<float>& a, int p) { return kTraceF32[p](a); }
 hipError_t trace(const TraceArgs<double>& a, int p) { return kTraceF64[p](a); }
+template <typename R> bool mass_built(int p);
+template <> bool mass_built<float>(int p) { return p >= 1 && p <= DGM_MAX_ORDER_F32 && kMassF32[p] != nullptr; }
+template <> bool mass_built<double>(int p) { return p >= 1 && p <= DGM_MAX_ORDER_F64 && kMassF64[p] != nullptr; }
+hipError_t mass(const MassArgs<float>& a, int p) { return kMassF32[p](a); }
+hipError_t mass(const MassArgs<double>& a, int p) { return kMassF64[p](a); }
+template <typename R> const R* vardev(const dgm_mesh* m, int fld);
+template <> const float* vardev<float>(const dgm_mesh* m, int fld) { return m->d_var32[fld]; }
+template <> const double* vardev<double>(const dgm_mesh* m, int fld) { return m->d_var64[fld]; }
 
 // Whether the kernels of order p are built for dtype.  The launcher tables are
 // indexed by order and hold nullptr for orders that were not generated.
@@ -455,6 +515,9 @@ int check_order(dgm_mesh* m, int dtype) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
   if (dtype != DGM_F32 && dtype != DGM_F64) return fail(DGM_ERR_ARG, "dtype must be DGM_F32 or DGM_F64");
   if (m->p < 1) return fail(DGM_ERR_STATE, "order not set (dgm_set_order)");
+  if (m->varmat && !(dtype == DGM_F32 ? mass_built<float>(m->pE) && mass_built<float>(m->p)
+                                      : mass_built<double>(m->pE) && mass_built<double>(m->p)))
+    return fail(DGM_ERR_ARG, "mass kernels of the orders not compiled for this dtype");
   if (mixed(m)) {
     if (!mixed_built(m->p, dtype))
       return fail(DGM_ERR_ARG, "mixed orders (" + std::to_string(m->pE) + ", " + std::to_string(m->p) +
@@ -469,6 +532,12 @@ int check_order(dgm_mesh* m, int dtype) {
 
 int check_equal_orders(const dgm_mesh* m, const char* what) {
   if (mixed(m)) return fail(DGM_ERR_STATE, std::string(what) + " needs equal orders for E and H");
+  return DGM_OK;
+}
+
+// Paths built for piecewise-constant material only (not for dgm_set_material_linear).
+int check_constant_material(const dgm_mesh* m, const char* what) {
+  if (m->varmat) return fail(DGM_ERR_STATE, std::string(what) + " needs piecewise-constant material (dgm_set_material)");
   return DGM_OK;
 }
 
@@ -502,6 +571,25 @@ int run_trace(dgm_mesh* m, const R* U, int fld, R* T, hipStream_t s) {
   a.blocks = (int)((m->K + 63) / 64);
   a.stream = s;
   HIP_TRY(trace(a, ford(m, fld)));
+  return DGM_OK;
+}
+
+// Approximate mass inverse of field fld (material linear on the elements):
+// V = (acc ? V : 0) + s P X, component by component (X, V in any one frame).
+template <typename R>
+int run_mass(dgm_mesh* m, const R* X, R* V, int fld, double sc, bool acc, hipStream_t s) {
+  const int p = ford(m, fld);
+  if (!mass_built<R>(p)) return fail(DGM_ERR_ARG, "mass kernel of order " + std::to_string(p) + " not built for this dtype");
+  MassArgs<R> a;
+  a.X = X;
+  a.V = V;
+  a.mat = vardev<R>(m, fld);
+  a.s = (R)sc;
+  a.acc = acc ? 1 : 0;
+  a.K = (int)m->K;
+  a.blocks = (int)((m->K + 63) / 64);
+  a.stream = s;
+  HIP_TRY(mass(a, p));
   return DGM_OK;
 }
 
@@ -547,19 +635,27 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
 
 // Covariant rate: out = d/dt of the other field from the covariant input `in`.
 // fld_u = 0: in = E, out = dH;  fld_u = 1: in = H, out = dE.
+// With a material linear on the elements (m->varmat) the metrics are those of unit
+// material and the approximate mass inverse follows (with_mass; without it the rate is
+// the unit-material one, which the dt estimate needs); the scratch then holds the
+// stored-frame copy of the input and the unit-material rate.
 template <typename R>
-int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF = nullptr, double fdt = 0.0) {
+int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF = nullptr, double fdt = 0.0,
+              bool with_mass = true) {
   const size_t n = field_len(m, fld_u), n_out = field_len(m, 1 - fld_u);
+  const bool var = m->varmat && with_mass;
   int rc;
-  if ((rc = ensure_scratch(m, n * sizeof(R)))) return rc;
+  if ((rc = ensure_scratch(m, (n + (var ? n_out : 0)) * sizeof(R)))) return rc;
   R* tmp = static_cast<R*>(m->d_scratch);
+  R* dst = var ? tmp + n : out;
   R* T[2];
   if ((rc = ensure_traces<R>(m, &T[0], &T[1]))) return rc;
   HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(R), hipMemcpyDeviceToDevice, s));
   if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
   if ((rc = run_trace<R>(m, tmp, fld_u, T[fld_u], s))) return rc;
-  if ((rc = fill<R>(out, n_out, (R)0, s))) return rc;
-  if ((rc = run_phase<R>(m, tmp, out, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt))) return rc;
+  if ((rc = fill<R>(dst, n_out, (R)0, s))) return rc;
+  if ((rc = run_phase<R>(m, tmp, dst, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt))) return rc;
+  if (var && (rc = run_mass<R>(m, dst, out, 1 - fld_u, 1.0, false, s))) return rc;
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
 
@@ -583,6 +679,7 @@ template <typename R>
 struct StepWork {
   R* TE = nullptr;
   R* TH = nullptr;
+  R* rate = nullptr;  // unit-material rate of the updated field (material linear on the elements)
   double* partial = nullptr;
   double* res = nullptr;
 };
@@ -611,6 +708,10 @@ template <typename R>
 int mesh_work(dgm_mesh* m, bool reductions, StepWork<R>* ws) {
   int rc;
   if ((rc = ensure_traces<R>(m, &ws->TE, &ws->TH))) return rc;
+  if (m->varmat) {
+    if ((rc = ensure_scratch(m, std::max(field_len(m, 0), field_len(m, 1)) * sizeof(R)))) return rc;
+    ws->rate = static_cast<R*>(m->d_scratch);
+  }
   if (reductions) {
     if ((rc = ensure_partial(m, kDotBlocks))) return rc;
     if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
@@ -640,8 +741,21 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
   for (int64_t it = 0; it < nsteps; ++it) {
     // H update from curl E (writes the traces of H), then E update from curl H
     // (writes the traces of E for the next step, except after the last one)
-    if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s, HF, dt))) return rc;
-    if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s, HF))) return rc;
+    if (m->varmat) {
+      // unit-material rate, then its approximate mass inverse into the field, then
+      // the traces of the updated field
+      if ((rc = fill<R>(ws.rate, nH, (R)0, s))) return rc;
+      if ((rc = run_phase<R>(m, E, ws.rate, 0, -1.0, TE, nullptr, s))) return rc;
+      if ((rc = run_mass<R>(m, ws.rate, H, 1, dt, true, s))) return rc;
+      if ((rc = run_trace<R>(m, H, 1, TH, s))) return rc;
+      if ((rc = fill<R>(ws.rate, n, (R)0, s))) return rc;
+      if ((rc = run_phase<R>(m, H, ws.rate, 1, 1.0, TH, nullptr, s))) return rc;
+      if ((rc = run_mass<R>(m, ws.rate, E, 0, dt, true, s))) return rc;
+      if (it + 1 < nsteps && (rc = run_trace<R>(m, E, 0, TE, s))) return rc;
+    } else {
+      if ((rc = run_phase<R>(m, E, H, 0, -dt, TE, TH, s, HF, dt))) return rc;
+      if ((rc = run_phase<R>(m, H, E, 1, dt, TH, it + 1 < nsteps ? TE : nullptr, s, HF))) return rc;
+    }
     if (w) {
       hipLaunchKernelGGL(dot_partial_kernel<R>, dim3(nb), dim3(kRedThreads), 0, s, (const R*)E, w, n, ws.partial);
       HIP_TRY(hipGetLastError());
@@ -705,6 +819,146 @@ int energy_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, dou
   return DGM_OK;
 }
 
+// Solves P x = b for field fld (P the approximate mass inverse, symmetric positive
+// definite per element and component) by conjugate gradients preconditioned with the
+// element's mean material; x starts at that preconditioner applied to b.  r, p, t are
+// work vectors of b's length, d four FP64 device scalars.  Stops once r.z has fallen
+// by tol^2 (checked on the host every 8 iterations) or after 400 iterations.
+template <typename T>
+int mass_solve(dgm_mesh* m, int fld, const T* b, T* x, T* r, T* p, T* t, double* d, double tol, hipStream_t s) {
+  const size_t n = field_len(m, fld);
+  const unsigned fb = flat_blocks(n);
+  const int nb = (int)std::min<size_t>(kDotBlocks, (n + kRedThreads - 1) / kRedThreads);
+  const T* mat = vardev<T>(m, fld);
+  int rc;
+  if ((rc = ensure_partial(m, nb))) return rc;
+  auto dot = [&](const T* A, const T* B, double* out) -> int {
+    hipLaunchKernelGGL(dot_partial_kernel<T>, dim3(nb), dim3(kRedThreads), 0, s, A, B, n, m->d_partial);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, m->d_partial, nb, out);
+    HIP_TRY(hipGetLastError());
+    return DGM_OK;
+  };
+  // x = M b, r = b - P x, t = M r, p = t, d[0] = r.t, d[3] = b.M b
+  hipLaunchKernelGGL(cg_precond_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, x, b, mat, n, (int)m->K);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if ((rc = run_mass<T>(m, x, r, fld, -1.0, true, s))) return rc;
+  hipLaunchKernelGGL(cg_precond_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, t, b, mat, n, (int)m->K);
+  HIP_TRY(hipGetLastError());
+  if ((rc = dot(b, t, d + 3))) return rc;
+  hipLaunchKernelGGL(cg_precond_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, t, r, mat, n, (int)m->K);
+  HIP_TRY(hipGetLastError());
+  if ((rc = dot(r, t, d + 0))) return rc;
+  HIP_TRY(hipMemcpyAsync(p, t, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  int cur = 0;
+  for (int it = 1; it <= 400; ++it) {
+    if ((rc = run_mass<T>(m, p, t, fld, 1.0, false, s))) return rc;
+    if ((rc = dot(p, t, d + 1))) return rc;
+    hipLaunchKernelGGL(cg_xr_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, x, r, (const T*)p, (const T*)t, n,
+                       (const double*)(d + cur), (const double*)(d + 1));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cg_precond_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, t, r, mat, n, (int)m->K);
+    HIP_TRY(hipGetLastError());
+    const int nxt = 2 - cur;  // r.z alternates between d[0] and d[2]
+    if ((rc = dot(r, t, d + nxt))) return rc;
+    hipLaunchKernelGGL(cg_p_kernel<T>, dim3(fb), dim3(kFlatThreads), 0, s, p, (const T*)t, n, (const double*)(d + nxt),
+                       (const double*)(d + cur));
+    HIP_TRY(hipGetLastError());
+    cur = nxt;
+    if (it % 8 == 0) {
+      double h[4];
+      HIP_TRY(hipMemcpyAsync(h, d, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (!std::isfinite(h[cur])) return fail(DGM_ERR_UNSTABLE, "non-finite residual in the mass solve");
+      if (h[cur] <= tol * tol * h[3]) return DGM_OK;
+    }
+  }
+  return fail(DGM_ERR_UNSTABLE, "mass solve did not converge in 400 iterations");
+}
+
+// W and Q with the approximate mass matrices (material linear on the elements).  With
+// M~ = P^{-1} per component and G the unit-material metric of the covariant inner
+// product, (a, M~ b) = (P^{-1} a)^T G b, so each energy needs one solve per field:
+// y = P^{-1} E, z = P^{-1} H, then W = 1/2 (y, G E) + 1/2 (z, G H) and Q has H_next in
+// place of H in the second term.  The solves and products run in FP64 whenever the
+// FP64 kernels of both orders are built (for FP32 fields after a copy to FP64).
+template <typename T, typename R>
+int energy_var_core(dgm_mesh* m, const R* E, const R* H, const R* Hq, double out[2], hipStream_t s) {
+  const size_t nE = field_len(m, 0), nH = field_len(m, 1), nmax = std::max(nE, nH);
+  const bool cast = !std::is_same<T, R>::value;
+  const size_t words = 5 * nmax + (cast ? nE + 2 * nH : 0);
+  T* w = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&w), words * sizeof(T) + 8 * sizeof(double), s));
+  T *y = w, *z = y + nmax, *r = z + nmax, *p = r + nmax, *t = p + nmax;
+  const T *Et = reinterpret_cast<const T*>(E), *Ht = reinterpret_cast<const T*>(H), *Hqt = reinterpret_cast<const T*>(Hq);
+  int rc = DGM_OK;
+  if (cast) {
+    T* c = t + nmax;
+    hipLaunchKernelGGL((cast_kernel<R, T>), dim3(flat_blocks(nE)), dim3(kFlatThreads), 0, s, c, E, nE);
+    hipLaunchKernelGGL((cast_kernel<R, T>), dim3(flat_blocks(nH)), dim3(kFlatThreads), 0, s, c + nE, H, nH);
+    hipLaunchKernelGGL((cast_kernel<R, T>), dim3(flat_blocks(nH)), dim3(kFlatThreads), 0, s, c + nE + nH, Hq, nH);
+    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "cast kernel launch failed");
+    Et = c;
+    Ht = c + nE;
+    Hqt = c + nE + nH;
+  }
+  double* d = reinterpret_cast<double*>(t + nmax + (cast ? nE + 2 * nH : 0));
+  const double tol = sizeof(T) == 8 ? 1e-13 : 1e-6;
+  if (!rc) rc = mass_solve<T>(m, 0, Et, y, r, p, t, d, tol, s);
+  if (!rc) rc = mass_solve<T>(m, 1, Ht, z, r, p, t, d, tol, s);
+  if (!rc) rc = mdot<T>(m, y, Et, 0, m->d_res + 0, s);
+  if (!rc) rc = mdot<T>(m, z, Ht, 1, m->d_res + 1, s);
+  if (!rc) rc = mdot<T>(m, z, Hqt, 1, m->d_res + 2, s);
+  double h[3] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(h, m->d_res, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(w, s);
+  const hipError_t e3 = hipStreamSynchronize(s);
+  if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
+  out[0] = 0.5 * h[0] + 0.5 * h[1];
+  out[1] = 0.5 * h[0] + 0.5 * h[2];
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return fail(DGM_ERR_UNSTABLE, "non-finite energy");
+  return DGM_OK;
+}
+
+template <typename R>
+int energy_var_impl(dgm_mesh* m, const R* E, const R* H, const R* Hn, double dt, double out[2], hipStream_t s) {
+  const size_t nH = field_len(m, 1);
+  int rc;
+  if (!m->d_res) HIP_TRY(hipMalloc(&m->d_res, 4 * sizeof(double)));
+  const R* Hq = Hn;
+  R* hn = nullptr;
+  if (!Hq) {
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&hn), nH * sizeof(R), s));
+    rc = rate_impl<R>(m, E, hn, 0, s);
+    if (!rc) {
+      hipLaunchKernelGGL(xpay_kernel<R>, dim3(flat_blocks(nH)), dim3(kFlatThreads), 0, s, hn, H, nH, dt);
+      if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "xpay kernel launch failed");
+    }
+    if (rc) {
+      hipFreeAsync(hn, s);
+      hipStreamSynchronize(s);
+      return rc;
+    }
+    Hq = hn;
+  }
+  if (mass_built<double>(m->pE) && mass_built<double>(m->p))
+    rc = energy_var_core<double, R>(m, E, H, Hq, out, s);
+  else
+    rc = energy_var_core<R, R>(m, E, H, Hq, out, s);
+  if (hn) {
+    const hipError_t e2 = hipFreeAsync(hn, s);
+    const hipError_t e3 = hipStreamSynchronize(s);
+    if (rc) return rc;
+    HIP_TRY(e2);
+    HIP_TRY(e3);
+  }
+  return rc;
+}
 
 int dense_ready(dgm_mesh* m, int prec, DenseOps** out) {
   const int q = prec == DGM_BF16 ? 0 : 1;
@@ -773,6 +1027,56 @@ int estimate_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt,
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
   const hipError_t e2 = hipFreeAsync(base, s);  // freed on every path
+  const hipError_t e3 = hipStreamSynchronize(s);
+  if (rc) return rc;
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  HIP_TRY(e3);
+  const double rho = -h[0] / h[1];
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DGM_ERR_UNSTABLE, "power iteration did not give a positive estimate");
+  if (rho_out) *rho_out = rho;
+  *dt = cfl * 2.0 / std::sqrt(rho);
+  return DGM_OK;
+}
+
+// The same power iteration with the approximate mass inverses (material linear on the
+// elements).  B = P_mu C P_eps C^T is self-adjoint in the inner product of
+// M~_mu = P_mu^{-1}, and with x = P_mu y that product is (x, x') = (y, G x') (G the
+// unit-material metric), so the iteration carries y beside x instead of solving:
+// w = unit-material dH(dE(x)) gives z = B x = P_mu w with z = P_mu w, i.e. the y of z is w.
+template <typename R>
+int estimate_var_impl(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* dt, double* rho_out, hipStream_t s) {
+  int rc = DGM_OK;
+  const size_t n = field_len(m, 1), nE = field_len(m, 0);  // x, z, y, w hold H; v holds E
+  R* x = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&x), (4 * n + nE) * sizeof(R) + 5 * sizeof(double), s));
+  R* const base = x;
+  R* z = x + n;
+  R* y = z + n;
+  R* w = y + n;
+  R* v = w + n;
+  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(v + nE) + 7) & ~uintptr_t(7));
+  const unsigned blocks = flat_blocks(n);
+  hipLaunchKernelGGL(splitmix_fill_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, y, n, (unsigned long long)seed);
+  if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "start vector kernel launch failed");
+  if (!rc) rc = run_mass<R>(m, y, x, 1, 1.0, false, s);
+  for (int it = 0; it < iters && !rc; ++it) {
+    if ((rc = rate_impl<R>(m, x, v, 1, s))) break;
+    if ((rc = rate_impl<R>(m, v, w, 0, s, nullptr, 0.0, false))) break;
+    if ((rc = run_mass<R>(m, w, z, 1, 1.0, false, s))) break;
+    if ((rc = mdot<R>(m, y, z, 1, d + 0, s))) break;
+    if ((rc = mdot<R>(m, y, x, 1, d + 1, s))) break;
+    if ((rc = mdot<R>(m, w, z, 1, d + 2, s))) break;
+    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, z, n, d + 2);
+    hipLaunchKernelGGL(scale_kernel<R>, dim3(blocks), dim3(kFlatThreads), 0, s, w, n, d + 2);
+    if (hipGetLastError() != hipSuccess) rc = fail(DGM_ERR_HIP, "scale kernel launch failed");
+    std::swap(x, z);
+    std::swap(y, w);
+  }
+  double h[3] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipMemcpyAsync(h, d, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipFreeAsync(base, s);
   const hipError_t e3 = hipStreamSynchronize(s);
   if (rc) return rc;
   HIP_TRY(e);
@@ -1010,6 +1314,7 @@ int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_
   m->F.resize(9 * nt);
   m->J.resize(nt);
   std::vector<int64_t> sorted(4 * nt);
+  m->perm.resize(4 * nt);
   for (int64_t e = 0; e < nt; ++e) {
     int64_t v[4];
     for (int q = 0; q < 4; ++q) {
@@ -1024,6 +1329,9 @@ int dgm_create_mesh(const double* verts, int64_t nv, const int64_t* tets, int64_
       delete m;
       return fail(DGM_ERR_MESH_DEGENERATE, "repeated vertex in element " + std::to_string(e));
     }
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 4; ++c)
+        if (tets[4 * e + c] == v[q]) m->perm[4 * e + q] = (unsigned char)c;
     double P[4][3], h = 0.0;
     for (int q = 0; q < 4; ++q) {
       sorted[4 * e + q] = v[q];
@@ -1143,6 +1451,7 @@ int dgm_destroy(dgm_mesh* m) {
   dense_free(m->dense[1]);
   hipFree(m->d_jump);
   hipFree(m->d_stab);
+  hipFree(m->d_var);
   delete m;
   return DGM_OK;
 }
@@ -1194,7 +1503,40 @@ int dgm_set_check_interval(dgm_mesh* m, int64_t every) {
 
 int dgm_set_material(dgm_mesh* m, const double* eps, const double* mu) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
-  return material_impl(m, eps, mu);
+  const int rc = material_impl(m, eps, mu);
+  if (!rc) m->varmat = false;
+  return rc;
+}
+
+int dgm_set_material_linear(dgm_mesh* m, const double* eps, const double* mu) {
+  if (!m) return fail(DGM_ERR_ARG, "null mesh");
+  const size_t K = (size_t)m->K;
+  // host images: eps then mu, (4,K) each at the sorted vertices, FP32 block then FP64
+  std::vector<float> v32(8 * K);
+  std::vector<double> v64(8 * K);
+  for (int fld = 0; fld < 2; ++fld) {
+    const double* src = fld == 0 ? eps : mu;
+    for (size_t e = 0; e < K; ++e)
+      for (int q = 0; q < 4; ++q) {
+        const double c = src ? src[4 * e + m->perm[4 * e + q]] : 1.0;
+        if (!(c > 0.0) || !std::isfinite(c))
+          return fail(DGM_ERR_MATERIAL, "material value must be finite and > 0 (element " + std::to_string(e) + ")");
+        v64[(4 * fld + q) * K + e] = c;
+        v32[(4 * fld + q) * K + e] = (float)c;
+      }
+  }
+  const size_t b32 = (8 * K * sizeof(float) + 255) & ~size_t(255);
+  if (!m->d_var) HIP_TRY(hipMalloc(&m->d_var, b32 + 8 * K * sizeof(double)));
+  char* base = static_cast<char*>(m->d_var);
+  HIP_TRY(hipMemcpy(base, v32.data(), v32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(base + b32, v64.data(), v64.size() * sizeof(double), hipMemcpyHostToDevice));
+  for (int fld = 0; fld < 2; ++fld) {
+    m->d_var32[fld] = reinterpret_cast<float*>(base) + 4 * fld * K;
+    m->d_var64[fld] = reinterpret_cast<double*>(base + b32) + 4 * fld * K;
+  }
+  const int rc = material_impl(m, nullptr, nullptr);  // unit-material metrics
+  m->varmat = rc == DGM_OK;
+  return rc;
 }
 
 int dgm_apply_curl(dgm_mesh* m, int dtype, const void* E, const void* H, void* dE, void* dH, hipStream_t s) {
@@ -1278,6 +1620,7 @@ int dgm_apply_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const v
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
+  if ((rc = check_constant_material(m, "the stabilised flux"))) return rc;
   if (((dH || dHF) && !E) || (dE && (!H || !HF))) return fail(DGM_ERR_ARG, "output requested without its input");
   const void* outs[3] = {dE, dH, dHF};
   for (const void* o : outs)
@@ -1294,6 +1637,7 @@ int dgm_step_stab(dgm_mesh* m, int dtype, void* E, void* H, void* HF, double dt,
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
+  if ((rc = check_constant_material(m, "the stabilised flux"))) return rc;
   if (!E || !H || !HF || E == H || E == HF || H == HF || nsteps < 0 || !std::isfinite(dt))
     return fail(DGM_ERR_ARG, "bad step arguments");
   if (nsteps == 0) return DGM_OK;
@@ -1314,6 +1658,7 @@ int dgm_energy_stab(dgm_mesh* m, int dtype, const void* E, const void* H, const 
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
+  if ((rc = check_constant_material(m, "the stabilised flux"))) return rc;
   if (!E || !H || !HF || !out || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad energy arguments");
   return dtype == DGM_F32 ? energy_stab_impl<float>(m, (const float*)E, (const float*)H, (const float*)HF, dt, out, s)
                           : energy_stab_impl<double>(m, (const double*)E, (const double*)H, (const double*)HF, dt, out, s);
@@ -1325,6 +1670,7 @@ int dgm_estimate_dt_stab(dgm_mesh* m, double cfl, int iters, uint64_t seed, doub
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the stabilised flux"))) return rc;
   if ((rc = stab_ready(m))) return rc;
+  if ((rc = check_constant_material(m, "the stabilised flux"))) return rc;
   if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
   return m->p <= DGM_MAX_ORDER_F64 ? estimate_stab_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
                                    : estimate_stab_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
@@ -1392,6 +1738,7 @@ extern "C" {
 int dgm_step_noalloc(dgm_mesh* m, int dtype, void* E, void* H, double dt, int64_t nsteps, hipStream_t s) {
   int rc = check_order(m, dtype);
   if (rc) return rc;
+  if ((rc = check_constant_material(m, "the allocation-free step"))) return rc;
   if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
   const size_t rsize = dtype == DGM_F32 ? sizeof(float) : sizeof(double);
   const size_t need = noalloc_bytes(m, rsize);
@@ -1422,7 +1769,10 @@ int dgm_energy(dgm_mesh* m, int dtype, const void* E, const void* H, const void*
   if (!E || !H || !out) return fail(DGM_ERR_ARG, "null argument");
   if (!Hn && dt == 0.0) Hn = H;  // Q = W when no step is taken
   int rc;
-  if (!Hn && (rc = check_order(m, dtype))) return rc;
+  if ((!Hn || m->varmat) && (rc = check_order(m, dtype))) return rc;
+  if (m->varmat)
+    return dtype == DGM_F32 ? energy_var_impl<float>(m, (const float*)E, (const float*)H, (const float*)Hn, dt, out, s)
+                            : energy_var_impl<double>(m, (const double*)E, (const double*)H, (const double*)Hn, dt, out, s);
   return dtype == DGM_F32 ? energy_impl<float>(m, (const float*)E, (const float*)H, (const float*)Hn, dt, out, s)
                           : energy_impl<double>(m, (const double*)E, (const double*)H, (const double*)Hn, dt, out, s);
 }
@@ -1432,6 +1782,9 @@ int dgm_estimate_dt(dgm_mesh* m, double cfl, int iters, uint64_t seed, double* d
   if (rc) return rc;
   if (!dt || iters < 1 || !(cfl > 0.0)) return fail(DGM_ERR_ARG, "bad estimate_dt arguments");
   // FP64 vectors where the order is compiled in FP64, FP32 vectors (FP64 dots) above it
+  if (m->varmat)
+    return m->pE <= DGM_MAX_ORDER_F64 ? estimate_var_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
+                                      : estimate_var_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
   return m->pE <= DGM_MAX_ORDER_F64 ? estimate_impl<double>(m, cfl, iters, seed, dt, rho_out, s)
                                    : estimate_impl<float>(m, cfl, iters, seed, dt, rho_out, s);
 }
@@ -1440,6 +1793,7 @@ int dgm_apply_curl_dense(dgm_mesh* m, int prec, const float* E, const float* H, 
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the dense variant"))) return rc;
+  if ((rc = check_constant_material(m, "the dense variant"))) return rc;
   if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
   if ((dH && !E) || (dE && !H)) return fail(DGM_ERR_ARG, "output requested without its input");
   if ((dH && (dH == E || dH == H)) || (dE && (dE == E || dE == H))) return fail(DGM_ERR_ARG, "outputs alias inputs");
@@ -1454,6 +1808,7 @@ int dgm_step_dense(dgm_mesh* m, int prec, float* E, float* H, double dt, int64_t
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "the dense variant"))) return rc;
+  if ((rc = check_constant_material(m, "the dense variant"))) return rc;
   if (prec != DGM_BF16 && prec != DGM_F16) return fail(DGM_ERR_ARG, "precision must be DGM_BF16 or DGM_F16");
   if (!E || !H || E == H || nsteps < 0 || !std::isfinite(dt)) return fail(DGM_ERR_ARG, "bad step arguments");
   if (nsteps == 0) return DGM_OK;
@@ -1600,6 +1955,7 @@ int dgm_batch_add(dgm_batch* b, dgm_mesh* m, float* E, float* H, double dt, int6
   int rc = check_order(m, DGM_F32);
   if (rc) return rc;
   if ((rc = check_equal_orders(m, "a batch slot"))) return rc;
+  if ((rc = check_constant_material(m, "a batch slot"))) return rc;
   for (const auto& q : b->active)
     if (q.m == m) return fail(DGM_ERR_ARG, "mesh handle already has an active slot");
   float *TE, *TH;

@@ -88,6 +88,20 @@ struct TraceArgs {
   hipStream_t stream;
 };
 
+// Approximate mass inverse of a field with a material linear on every element:
+// V = (acc ? V : 0) + s * P X per component, P as in the generated dgm_mass_p{p}.
+template <typename R>
+struct MassArgs {
+  const R* X;       // (3,N,K) input (any frame: P acts on every component alike)
+  R* V;             // (3,N,K) output; may not alias X
+  const R* mat;     // (4,K) material at the element's vertices, sorted by global id
+  R s;              // scale
+  int acc;          // nonzero: accumulate into V
+  int K;
+  int blocks;       // ceil(K / 64); the launch has 3 * blocks workgroups (one per component)
+  hipStream_t stream;
+};
+
 // One mesh of a batched launch (FP32 fields in the stored frame).
 struct BatchSlot {
   const void* E;    // (3,N,K)

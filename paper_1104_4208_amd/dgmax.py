@@ -45,6 +45,7 @@ SIGNATURES = {
     "dgm_set_orders": (_c_i, [_c_p, _c_i, _c_i]),
     "dgm_orders": (_c_i, [_c_p, _pi, _pi]),
     "dgm_set_material": (_c_i, [_c_p, _pd, _pd]),
+    "dgm_set_material_linear": (_c_i, [_c_p, _pd, _pd]),
     "dgm_set_check_interval": (_c_i, [_c_p, _c_i64]),
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
@@ -210,6 +211,20 @@ class Mesh:
         ea, ep = arr(eps)
         ma, mp = arr(mu)
         _check(load_library().dgm_set_material(self._h, ep, mp))
+        return self
+
+    def set_material_linear(self, eps=None, mu=None):
+        """Material linear inside every element (Section 3.3.2): (K, 4) values at each
+        element's vertices, in the order the element was given; None means 1."""
+        def arr(x):
+            if x is None:
+                return None, None
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (self.K, 4)))
+            return a, a.ctypes.data_as(_pd)
+
+        ea, ep = arr(eps)
+        ma, mp = arr(mu)
+        _check(load_library().dgm_set_material_linear(self._h, ep, mp))
         return self
 
     def set_check_interval(self, every: int):

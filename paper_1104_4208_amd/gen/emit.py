@@ -30,6 +30,7 @@ import os
 
 import numpy as np
 
+from . import mass as MS
 from . import tables as TB
 
 
@@ -1337,6 +1338,8 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
         units.append(_write_if_changed(os.path.join(outdir, f"batch_p{p}.hip"), "\n".join(tb) + "\n"))
         if p + 1 in orders:
             units.append(_emit_mixed(outdir, p))
+        _write_if_changed(os.path.join(outdir, f"mass_p{p}.inc"), MS.emit_mass(p))
+        units.append(_write_if_changed(os.path.join(outdir, f"mass_p{p}.hip"), MS.emit_unit(p, p <= F64_MAX_ORDER)))
     fr = TB.frame()
     A, Ai = fr["A"], fr["Ainv"]
     lines = ["// Generated by gen/emit.py: derivative frame and compiled orders.",
@@ -1355,6 +1358,10 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
         if p <= F64_MAX_ORDER:
             decl.append(f"hipError_t dgm_launch_trace_p{p}_f64(const TraceArgs<double>& a);")
     lines += decl
+    for p in orders:
+        lines.append(f"hipError_t dgm_launch_mass_p{p}_f32(const MassArgs<float>& a);")
+        if p <= F64_MAX_ORDER:
+            lines.append(f"hipError_t dgm_launch_mass_p{p}_f64(const MassArgs<double>& a);")
     for p in orders:
         lines.append(f"hipError_t dgm_launch_batch_p{p}_f32(const BatchArgs& a);")
         if p + 1 in orders:
@@ -1427,6 +1434,8 @@ def launcher_tables(orders):
         table("hipError_t (*const kPhaseF32[{n}])(const PhaseArgs<float>&)", "dgm_launch_phase_p{p}_f32", lambda p: True),
         table("hipError_t (*const kPhaseF64[{n}])(const PhaseArgs<double>&)", "dgm_launch_phase_p{p}_f64", f64),
         table("hipError_t (*const kBatchF32[{n}])(const BatchArgs&)", "dgm_launch_batch_p{p}_f32", lambda p: True),
+        table("hipError_t (*const kMassF32[{n}])(const MassArgs<float>&)", "dgm_launch_mass_p{p}_f32", lambda p: True),
+        table("hipError_t (*const kMassF64[{n}])(const MassArgs<double>&)", "dgm_launch_mass_p{p}_f64", f64),
     ]
 
 

@@ -234,3 +234,40 @@ def op_counts(p: int):
     nD = [int((D != 0).sum()) for D in t.D]
     nT = [int((T != 0).sum()) for T in t.T]
     return dict(p=p, N=t.N, NF=t.NF, nnz_D=nD, nnz_T=nT)
+
+
+@functools.lru_cache(maxsize=None)
+def mass_factors(p: int):
+    """Sum-factorisation tables of the approximate mass inverse (Section 3.3.2) on the
+    collapsed Gauss rule with q = p + 1 points per direction (exact on products of two
+    basis functions).  At the point (a, b, c) of the collapsed coordinates
+        phi_ijk = s_ijk ((1-a)/2)^(i+j) P_k^{(2i+2j+2,0)}(a) ((1-b)/2)^i P_j^{(2i+1,0)}(b) P_i(c)
+    so phi = C1[r, qa] * Fb[i, j, qb] * Fc[i, qc] with C1 the s- and a-factor of mode r.
+    Returns dict(q, C1 (N, q), Fb (p+1, p+1, q), Fc (p+1, q), W (q, q, q) the weights,
+    lam (q, q, q, 4) the barycentric coordinates of the points); build checks the product
+    against the basis values."""
+    from scipy.special import eval_jacobi, roots_jacobi
+
+    t = build(p)
+    q = p + 1
+    xa, _ = roots_jacobi(q, 2, 0)
+    xb, _ = roots_jacobi(q, 1, 0)
+    xc, _ = roots_jacobi(q, 0, 0)
+    C1 = np.zeros((t.N, q))
+    for r, (i, j, k) in enumerate(t.modes):
+        s = np.sqrt((2 * i + 1) * (2 * i + 2 * j + 2) * (2 * i + 2 * j + 2 * k + 3))
+        C1[r] = s * ((1 - xa) / 2) ** (i + j) * eval_jacobi(k, 2 * i + 2 * j + 2, 0, xa)
+    Fb = np.zeros((p + 1, p + 1, q))
+    Fc = np.zeros((p + 1, q))
+    for i in range(p + 1):
+        Fc[i] = eval_jacobi(i, 0, 0, xc)
+        for j in range(p + 1 - i):
+            Fb[i, j] = ((1 - xb) / 2) ** i * eval_jacobi(j, 2 * i + 1, 0, xb)
+    pts, w = B.collapsed_rule_tet(q)
+    V = B.volume_values(p, pts).reshape(t.N, q, q, q)
+    for r, (i, j, k) in enumerate(t.modes):
+        prod = C1[r][:, None, None] * Fb[i, j][None, :, None] * Fc[i][None, None, :]
+        if np.abs(prod - V[r]).max() > 1e-11 * max(1.0, np.abs(V[r]).max()):
+            raise AssertionError("mass factors do not reproduce the basis")
+    lam = np.stack([1 - pts.sum(1), pts[:, 0], pts[:, 1], pts[:, 2]], axis=1).reshape(q, q, q, 4)
+    return dict(q=q, C1=C1, Fb=Fb, Fc=Fc, W=w.reshape(q, q, q), lam=lam)

@@ -1,0 +1,257 @@
+"""Material linear inside the elements through the approximate mass inverse (Section
+3.3.2): the HIP path (dgm_set_material_linear and the generated dgm_mass_p{p} kernels)
+against the oracle's VarMaterialSolver, element by element, through the C-ABI.
+
+The approximate inverse depends on the reference map its quadrature rule is laid on;
+the library uses the map with vertices sorted by global id, so the oracle is given the
+sorted elements with the vertex values permuted alike.  Tolerances as for the constant
+material: FP64 1e-10, FP32 1e-5 relative to the largest value; runs in the energy norm;
+the leapfrog invariant in the inner product of M~ = P^{-1} (exactly conserved by the
+scheme, Section 3)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import frames, patch, rel_err, sort_tets
+from oracle.mixed import MixedSolver
+from oracle.varcoef import VarMaterialSolver
+from paper_1104_4208_amd.gen.basis import volume_modes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1104_4208_amd as P  # noqa: E402
+
+
+def sorted_values(tets, vals):
+    """(K,4) vertex values in the caller's order -> in sorted-vertex order."""
+    order = np.argsort(np.asarray(tets), axis=1)
+    return np.take_along_axis(np.asarray(vals, float), order, axis=1)
+
+
+def mode_perm(p):
+    idx = {m: r for r, m in enumerate(oracle.mode_list(p))}
+    pm = np.array([idx[m] for m in volume_modes(p)])
+    ipm = np.empty_like(pm)
+    ipm[pm] = np.arange(len(pm))
+    return pm, ipm
+
+
+class VarPair:
+    """The oracle's variable-material solver on the library's (sorted) elements."""
+
+    def __init__(self, verts, tets, p, eps_v, mu_v):
+        ts = sort_tets(tets)
+        self.s = VarMaterialSolver(oracle.build_mesh(np.asarray(verts, float), ts), p,
+                                   sorted_values(tets, eps_v), sorted_values(tets, mu_v))
+        self.F = frames(verts, tets)
+        self.pm, self.ipm = mode_perm(p)
+
+    def to_cov(self, phys):
+        return np.einsum("kji,kmj->imk", self.F, phys)[:, self.pm, :]
+
+    def to_phys(self, cov):
+        c = np.asarray(cov, float)[:, self.ipm, :]
+        return np.einsum("kji,jmk->kmi", np.linalg.inv(self.F), c)
+
+    def invariant(self, E, H, dt):
+        Hn = H + dt * self.s.rhs_h(E)
+        return 0.5 * self.s.mass_dot(E, E, "E") + 0.5 * self.s.mass_dot(H, Hn, "H")
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+MESHES = {
+    "one": lambda rng: synth.single_tet(np.array([[0.1, 0, 0], [1, 0.2, 0], [0, 1.1, 0.1], [0.2, 0.1, 0.9]])),
+    "two_unsorted": lambda rng: synth.two_tets(rng),
+    "cube1": lambda rng: synth.kuhn_mesh(1),
+    "jit2": lambda rng: synth.kuhn_mesh(2, 0.1, rng),
+    "jit3_ragged": lambda rng: synth.kuhn_mesh(3, 0.1, rng),
+}
+
+
+def smooth_material(verts, tets):
+    """Continuous material fields sampled at the vertices (caller's order)."""
+    x = np.asarray(verts, float)[np.asarray(tets)]
+    eps = 1.5 + 0.5 * np.sin(2.0 * x[..., 0]) + 0.4 * x[..., 1]
+    mu = 1.0 + 0.3 * x[..., 2]
+    return eps, mu
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mesh", list(MESHES))
+def test_var_apply_curl_parity(mesh, p, dtype):
+    if dtype == "f64" and p > P.max_order(P.DGM_F64):
+        pytest.skip("order not compiled for FP64")
+    if p >= 5 and mesh == "jit3_ragged":
+        pytest.skip("covered at lower orders; keeps the oracle fast")
+    rng = np.random.default_rng(700 + p)
+    verts, tets = MESHES[mesh](rng)
+    K = tets.shape[0]
+    eps_v, mu_v = rng.uniform(1, 4, (K, 4)), rng.uniform(1, 2, (K, 4))  # jumps between elements too
+    pr = VarPair(verts, tets, p, eps_v, mu_v)
+    E = rng.standard_normal((K, pr.s.N, 3))
+    H = rng.standard_normal((K, pr.s.N, 3))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    m = P.Mesh(verts, tets).set_order(p).set_material_linear(eps_v, mu_v)
+    dE, dH = m.apply_curl(dev(pr.to_cov(E), tdt), dev(pr.to_cov(H), tdt))
+    ee = rel_err(host(dE), pr.to_cov(pr.s.rhs_e(H)))
+    eh = rel_err(host(dH), pr.to_cov(pr.s.rhs_h(E)))
+    print(f"var p={p} {mesh} {dtype}: dE {ee:.2e} dH {eh:.2e}")
+    assert ee < tol and eh < tol
+
+
+@pytest.mark.parametrize("p", [2, 5])
+def test_var_constant_values_equal_the_flat_method(p):
+    """Vertex values equal on each element: the same rates as dgm_set_material (the
+    approximate inverse is then exact), and dgm_set_material switches back."""
+    rng = np.random.default_rng(71)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K = tets.shape[0]
+    eps, mu = rng.uniform(1, 4, K), rng.uniform(1, 2, K)
+    E = dev(rng.standard_normal((3, P.num_modes(p), K)), torch.float64)
+    H = dev(rng.standard_normal((3, P.num_modes(p), K)), torch.float64)
+    m = P.Mesh(verts, tets).set_order(p).set_material(eps, mu)
+    dE0, dH0 = m.apply_curl(E, H)
+    m.set_material_linear(np.repeat(eps[:, None], 4, 1), np.repeat(mu[:, None], 4, 1))
+    dE1, dH1 = m.apply_curl(E, H)
+    assert rel_err(host(dE1), host(dE0)) < 1e-12 and rel_err(host(dH1), host(dH0)) < 1e-12
+    m.set_material(eps, mu)
+    dE2, dH2 = m.apply_curl(E, H)
+    assert torch.equal(dE2, dE0) and torch.equal(dH2, dH0)
+
+
+@pytest.mark.parametrize("dtype,tol,qtol", [(torch.float64, 1e-10, 1e-12), (torch.float32, 1e-5, 1e-6)])
+def test_var_run_against_oracle(dtype, tol, qtol):
+    """TE101 on the jittered 48-tet cube at p = 3 with smooth eps and mu: 80 leapfrog
+    steps against the oracle's, energies against the oracle's M~ products, and the
+    invariant Q conserved."""
+    rng = np.random.default_rng(73)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    eps_v, mu_v = smooth_material(verts, tets)
+    pr = VarPair(verts, tets, 3, eps_v, mu_v)
+    s = pr.s
+    E = s.project(synth.te101().E)
+    H = np.zeros_like(E)
+    dt = 0.9 / math.sqrt(s.spectral_radius(40, synth.splitmix64(73, H.size)))
+    m = P.Mesh(verts, tets).set_order(3).set_material_linear(eps_v, mu_v)
+    Eg, Hg = dev(pr.to_cov(E), dtype), dev(pr.to_cov(H), dtype)
+    W0, Q0 = m.energy(Eg, Hg, dt=dt)
+    Q0o = pr.invariant(E, H, dt)
+    assert abs(Q0 - Q0o) < (1e-10 if dtype == torch.float64 else 1e-6) * Q0o
+    worst, drift = 0.0, 0.0
+    for _ in range(8):
+        m.step(Eg, Hg, dt, 10)
+        E, H = s.step(E, H, dt, 10)
+        worst = max(worst, s.rel_error(pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), E, H))
+        W, Q = m.energy(Eg, Hg, dt=dt)
+        drift = max(drift, abs(Q - Q0) / Q0)
+    Qo = pr.invariant(E, H, dt)
+    print(f"var run {dtype}: worst energy-norm error {worst:.2e}, Q drift {drift:.2e}, "
+          f"Q vs oracle {abs(Q - Qo) / Qo:.2e}")
+    assert worst < tol
+    assert drift < qtol
+    assert abs(Q - Qo) < (1e-10 if dtype == torch.float64 else 1e-5) * Qo
+
+
+def test_var_estimate_dt_and_spectrum():
+    """The power iteration in the M~ inner product approaches the largest eigenvalue of
+    the assembled operator from below (within 1e-3 after 200 iterations)."""
+    rng = np.random.default_rng(75)
+    verts, tets = synth.kuhn_mesh(1)
+    eps_v, mu_v = rng.uniform(1, 4, (6, 4)), rng.uniform(1, 2, (6, 4))
+    pr = VarPair(verts, tets, 2, eps_v, mu_v)
+    Ah, Ae = pr.s.assemble()
+    rho = float(np.linalg.eigvals(-(Ah @ Ae)).real.max())
+    m = P.Mesh(verts, tets).set_order(2).set_material_linear(eps_v, mu_v)
+    dt, est = m.estimate_dt(cfl=0.5, iters=200, seed=7)
+    print(f"var rho: library {est:.8e}, assembled oracle {rho:.8e}")
+    assert rho * (1 - 1e-3) < est < rho * (1 + 1e-10)
+
+
+def test_var_mixed_orders():
+    """Mixed orders (E of degree 3, H of degree 2) with the material linear on the
+    elements: the oracle's unit-material mixed rates followed by its approximate
+    inverses of the two orders."""
+    rng = np.random.default_rng(77)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K = tets.shape[0]
+    eps_v, mu_v = rng.uniform(1, 4, (K, 4)), rng.uniform(1, 2, (K, 4))
+    ts = sort_tets(tets)
+    mesh = oracle.build_mesh(verts, ts)
+    mix = MixedSolver(mesh, 3, 2, None, None)
+    invE = VarMaterialSolver(mesh, 3, sorted_values(tets, eps_v), sorted_values(tets, mu_v))
+    invH = VarMaterialSolver(mesh, 2, sorted_values(tets, eps_v), sorted_values(tets, mu_v))
+    F = frames(verts, tets)
+    pmE, ipmE = mode_perm(3)
+    pmH, ipmH = mode_perm(2)
+    cov = lambda phys, pm: np.einsum("kji,kmj->imk", F, phys)[:, pm, :]
+    E = rng.standard_normal((K, mix.NE, 3))
+    H = rng.standard_normal((K, mix.NH, 3))
+    J = invE.absJ[:, None, None]
+    refE = invE.approx_inverse(mix.rhs_e(H) * J, "E")
+    refH = invH.approx_inverse(mix.rhs_h(E) * J, "H")
+    m = P.Mesh(verts, tets).set_orders(3, 2).set_material_linear(eps_v, mu_v)
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        dE, dH = m.apply_curl(dev(cov(E, pmE), dtype), dev(cov(H, pmH), dtype))
+        ee, eh = rel_err(host(dE), cov(refE, pmE)), rel_err(host(dH), cov(refH, pmH))
+        print(f"var mixed (3,2) {dtype}: dE {ee:.2e} dH {eh:.2e}")
+        assert ee < tol and eh < tol
+
+
+def test_var_full_size_sampled():
+    """The 32^3 x 6 jittered cube at p = 6 (196,608 tets), FP32, material linear on every
+    element with eps jumping between 1 and 4 times a smooth factor: one application,
+    sampled elements against the oracle on their patch meshes."""
+    rng = np.random.default_rng(79)
+    w = synth.WORKLOADS["cube32_p6_f32"]
+    d = synth.build_workload(w)
+    verts, tets = d["verts"], d["tets"]
+    K = tets.shape[0]
+    x = verts[tets]
+    eps_v = d["eps"][:, None] * (1.0 + 0.25 * np.sin(3.0 * x[..., 0]) * np.cos(2.0 * x[..., 2]))
+    mu_v = 1.0 + 0.2 * x[..., 1]
+    m = P.Mesh(verts, tets).set_order(w.p).set_material_linear(eps_v, mu_v)
+    N = P.num_modes(w.p)
+    Ecov = rng.standard_normal((3, N, K)).astype(np.float32)
+    Hcov = rng.standard_normal((3, N, K)).astype(np.float32)
+    dE, dH = m.apply_curl(dev(Ecov, torch.float32), dev(Hcov, torch.float32))
+    dE, dH = host(dE), host(dH)
+    centers = np.unique(np.concatenate([rng.integers(0, K, 8), [0, K - 1]]))
+    keep, ptets, pos = patch(tets, centers)
+    pr = VarPair(verts, ptets, w.p, sorted_values(tets, eps_v)[keep], sorted_values(tets, mu_v)[keep])
+    ref_dE = pr.to_cov(pr.s.rhs_e(pr.to_phys(Hcov[:, :, keep].astype(np.float64))))[:, :, pos]
+    ref_dH = pr.to_cov(pr.s.rhs_h(pr.to_phys(Ecov[:, :, keep].astype(np.float64))))[:, :, pos]
+    ee, eh = rel_err(dE[:, :, centers], ref_dE), rel_err(dH[:, :, centers], ref_dH)
+    print(f"var 32^3 p6 sampled {len(centers)}: dE {ee:.2e} dH {eh:.2e}")
+    assert ee < 1e-5 and eh < 1e-5
+
+
+def test_var_rejected_where_unsupported():
+    verts, tets = synth.kuhn_mesh(1)
+    m = P.Mesh(verts, tets).set_order(2)
+    with pytest.raises(P.DGMError, match="DGM_ERR_MATERIAL"):
+        m.set_material_linear(np.full((6, 4), -1.0))
+    m.set_material_linear(np.full((6, 4), 2.0)).set_stab_alpha(1.0)
+    E, H = m.zeros(torch.float32), m.zeros(torch.float32)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.energy_stab(E, H, m.face_zeros(torch.float32))
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.apply_curl_dense(E, H)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.step_noalloc(E, H, 1e-3, 1)
+    b = P.Batch(chunk=2)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        b.add(m, E, H, 1e-3, 2)
