@@ -23,7 +23,8 @@ without packed FP32.  roofline.traffic and alu.valu_issue_frac: from the committ
 counter summary when it was taken on the current kernel source.  The run then
 continues to the configuration's 500 steps for the drift of the leapfrog
 invariant.  stabilized_flux: the stabilised central flux (Section 2.1) on the same
-mesh; mixed_orders: E of degree 7, H of degree 6 (Section 2) on the same mesh.  dense_variant: the p = 8 matrix-core comparison.  serving: the 256-request
+mesh; mixed_orders: E of degree 7, H of degree 6 (Section 2) on the same mesh; linear_material:
+eps and mu linear inside the elements through the approximate mass inverse (Section 3.3.2).  dense_variant: the p = 8 matrix-core comparison.  serving: the 256-request
 trace, batched against sequential.  cpu_baseline: the FP64 oracle timed on a
 bounded sample of the same workload (smaller cube, same order and recipe); the
 same leg (the only code here that runs the oracle) reports under "accuracy" the
@@ -94,6 +95,7 @@ def parse():
     ap.add_argument("--no-stab", action="store_true", help="skip the stabilised-flux leg")
     ap.add_argument("--stab-steps", type=int, default=100, help="steps of the stabilised and mixed-order legs")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-order leg")
+    ap.add_argument("--no-var", action="store_true", help="skip the variable-material leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run three plain device copies of this many MiB (scale reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -306,6 +308,55 @@ def mixed_leg(w, d, steps: int, pE: int = 7, pH: int = 6):
             "steps_total": steps + 8}
 
 
+def var_leg(w, d, E0, steps: int):
+    """Material linear inside the elements (Section 3.3.2) on the benchmark mesh, FP32, p = 6:
+    eps at the vertices = the element's eps in {1, 4} times 1 + 0.25 sin(3x) cos(2z), mu =
+    1 + 0.2 y.  A step is, per field, the unit-material phase (rate into a work buffer), the
+    approximate mass inverse added into the field (dgm_mass_p6, sum factorisation on the 7^3
+    collapsed Gauss points) and the field's traces.  Reports time per step, the drift of the
+    invariant in the M~ inner product (energies by CG solves), and the mass kernel's emitted
+    flops per element (its duration is in the committed kernel-trace summary)."""
+    import torch
+
+    import paper_1104_4208_amd as P
+    from paper_1104_4208_amd.gen import mass as MS
+
+    K, p = d["tets"].shape[0], w.p
+    N = P.num_modes(p)
+    x = d["verts"][d["tets"]]
+    eps_v = d["eps"][:, None] * (1.0 + 0.25 * np.sin(3.0 * x[..., 0]) * np.cos(2.0 * x[..., 2]))
+    mu_v = 1.0 + 0.2 * x[..., 1]
+    m = P.Mesh(d["verts"], d["tets"]).set_order(p).set_material_linear(eps_v, mu_v)
+    dt, rho = m.estimate_dt(cfl=0.5, iters=20, seed=w.seed)
+    E = torch.tensor(np.ascontiguousarray(E0), dtype=torch.float32, device="cuda")
+    H = torch.zeros_like(E)
+    _, Q0 = m.energy(E, H, dt=dt)
+    m.step(E, H, dt, 5)
+
+    def timed(nsteps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        m.step(E, H, dt, nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one = min(timed(1) for _ in range(3))
+    t = timed(steps)
+    _, Q1 = m.energy(E, H, dt=dt)
+    step_s = (t - one) / (steps - 1)
+    mc = MS.mass_cost(p)
+    del E, H, m
+    torch.cuda.empty_cache()
+    return {"workload": "pec_cube_cavity_kuhn32_p6_fp32_linear_material", "dt": dt, "rho": rho, "steps": steps,
+            "ms_per_step": step_s * 1e3, "dof_updates_per_s": 6 * N * K / step_s,
+            "mass_kernel": {"name": "dgm_mass_p6<float>", "flops_per_element": mc["flops"],
+                            "flops_per_launch": mc["flops"] * K,
+                            "algorithmic_bytes_per_element": 3 * N * 4 * 3 + 16},
+            "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps + 8}
+
+
 def dense_comparison(steps: int):
     """p = 8 workload (24^3 x 6 = 82,944 tets, random modal data, seed 4): the FP32
     sparse path against the dense matrix-core variant with BF16 and FP16 operands.
@@ -468,6 +519,8 @@ def main():
         out["stabilized_flux"] = stab_leg(w, d, E0, a.stab_steps)
     if not a.no_mixed:
         out["mixed_orders"] = mixed_leg(w, d, a.stab_steps)
+    if not a.no_var:
+        out["linear_material"] = var_leg(w, d, E0, a.stab_steps)
     if not a.no_dense:
         out["dense_variant"] = dense_comparison(a.dense_steps)
     if not a.no_serve:
