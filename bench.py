@@ -501,7 +501,7 @@ def main():
         "config": dict(WORKLOAD, dt=dt, rho=rho),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "dgm_phase_p6<float, true, false>", "phase_us": phase_s * 1e6,
+                     "kernel": "dgm_phase_p6<float, true, false, false>", "phase_us": phase_s * 1e6,
                      "bytes_per_launch": bytes_launch, "alu": alu},
         "energy": {"W0": W0, "Q0": Q0, "Q_end": Q1, "Q_rel_drift": abs(Q1 - Q0) / Q0, "steps_total": steps_done},
     }

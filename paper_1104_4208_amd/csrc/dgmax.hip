@@ -604,9 +604,11 @@ const double* SCdev<double>(const dgm_mesh* m) { return m->d_SC64; }
 
 // With HF (stabilised flux): the H phase (fld_u 0) advances the face unknowns by fdt
 // times their rate; the E phase reads them.
+// overwrite: V = sdt * rate without reading V (central flux, equal orders only; the
+// callers check that).
 template <typename R>
 int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin, R* Tout, hipStream_t s,
-              R* HF = nullptr, double fdt = 0.0) {
+              R* HF = nullptr, double fdt = 0.0, bool overwrite = false) {
   PhaseArgs<R> a;
   a.U = U;
   a.V = V;
@@ -624,6 +626,8 @@ int run_phase(dgm_mesh* m, const R* U, R* V, int fld_u, double sdt, const R* Tin
   a.HF = HF;
   a.SC = HF ? SCdev<R>(m) : nullptr;
   a.fdt = (R)fdt;
+  a.overwrite = overwrite ? 1 : 0;
+  if (overwrite && (HF || mixed(m) || Tout)) return fail(DGM_ERR_STATE, "rate-only phase needs the central flux and equal orders");
   if (mixed(m)) {
     if (HF) return fail(DGM_ERR_STATE, "the stabilised flux needs equal orders");
     HIP_TRY(mix(a, m->p, fld_u));
@@ -653,8 +657,10 @@ int rate_impl(dgm_mesh* m, const R* in, R* out, int fld_u, hipStream_t s, R* HF 
   HIP_TRY(hipMemcpyAsync(tmp, in, n * sizeof(R), hipMemcpyDeviceToDevice, s));
   if ((rc = convert<R>(m, tmp, fld_u, true, s))) return rc;
   if ((rc = run_trace<R>(m, tmp, fld_u, T[fld_u], s))) return rc;
-  if ((rc = fill<R>(dst, n_out, (R)0, s))) return rc;
-  if ((rc = run_phase<R>(m, tmp, dst, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt))) return rc;
+  // the phase writes the rate into dst directly where it can, else adds it to zeros
+  const bool direct = !HF && !mixed(m);
+  if (!direct && (rc = fill<R>(dst, n_out, (R)0, s))) return rc;
+  if ((rc = run_phase<R>(m, tmp, dst, fld_u, fld_u == 0 ? -1.0 : 1.0, T[fld_u], nullptr, s, HF, fdt, direct))) return rc;
   if (var && (rc = run_mass<R>(m, dst, out, 1 - fld_u, 1.0, false, s))) return rc;
   return convert<R>(m, out, 1 - fld_u, false, s);
 }
@@ -744,12 +750,13 @@ int step_impl(dgm_mesh* m, R* E, R* H, double dt, int64_t nsteps, hipStream_t s,
     if (m->varmat) {
       // unit-material rate, then its approximate mass inverse into the field, then
       // the traces of the updated field
-      if ((rc = fill<R>(ws.rate, nH, (R)0, s))) return rc;
-      if ((rc = run_phase<R>(m, E, ws.rate, 0, -1.0, TE, nullptr, s))) return rc;
+      const bool direct = !mixed(m);
+      if (!direct && (rc = fill<R>(ws.rate, nH, (R)0, s))) return rc;
+      if ((rc = run_phase<R>(m, E, ws.rate, 0, -1.0, TE, nullptr, s, nullptr, 0.0, direct))) return rc;
       if ((rc = run_mass<R>(m, ws.rate, H, 1, dt, true, s))) return rc;
       if ((rc = run_trace<R>(m, H, 1, TH, s))) return rc;
-      if ((rc = fill<R>(ws.rate, n, (R)0, s))) return rc;
-      if ((rc = run_phase<R>(m, H, ws.rate, 1, 1.0, TH, nullptr, s))) return rc;
+      if (!direct && (rc = fill<R>(ws.rate, n, (R)0, s))) return rc;
+      if ((rc = run_phase<R>(m, H, ws.rate, 1, 1.0, TH, nullptr, s, nullptr, 0.0, direct))) return rc;
       if ((rc = run_mass<R>(m, ws.rate, E, 0, dt, true, s))) return rc;
       if (it + 1 < nsteps && (rc = run_trace<R>(m, E, 0, TE, s))) return rc;
     } else {

@@ -76,6 +76,8 @@ struct PhaseArgs {
   R* HF = nullptr;
   const R* SC = nullptr;
   R fdt = R(0);
+  // nonzero: V is only written, V = sdt * rate (central flux, equal orders, no Tout)
+  int overwrite = 0;
 };
 
 template <typename R>

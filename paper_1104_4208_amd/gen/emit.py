@@ -700,7 +700,7 @@ def _lift_job(a_, t, Lp, rows, ind):
     if early:
         a_(ind + "  // old values of the updated rows")
         for j, b in enumerate(rows):
-            a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = ldf<ST>(&V[({k * N + b}) * Ks + el])" for k in range(3)) + ";")
+            a_(ind + "  const R " + ", ".join(f"vo{k}_{j} = RATE ? R(0) : ldf<ST>(&V[({k * N + b}) * Ks + el])" for k in range(3)) + ";")
     jd = lambda f, k, m: f"wl[({(f * 2 + k) * NF + m}) * {LANES} + lane]"
     for f in range(4):
         if _lift_factored(t, Lp, f, rows):
@@ -756,7 +756,7 @@ def _lift_job(a_, t, Lp, rows, ind):
     # the new values stay in the accumulator slots (the traces of V are formed from them)
     for j, b in enumerate(rows):
         for k in range(3):
-            old = f"vo{k}_{j}" if early else f"ldf<ST>(&V[({k * N + b}) * Ks + el])"
+            old = f"vo{k}_{j}" if early else f"(RATE ? R(0) : ldf<ST>(&V[({k * N + b}) * Ks + el]))"
             _count(2)
             a_(ind + f"  acc{k}_{j} = {old} + sdt * acc{k}_{j};")
     a_(ind + "  if (act) {")
@@ -1180,7 +1180,8 @@ def emit_phase(p: int, pU: int = None, pV: int = None, name: str = None) -> str:
         a_(f"static_assert(trace_face_stride({tV.NF}) == {trace_strides(tV.NF)[0]}, \"trace layout of V\");")
     a_("// ST: field loads and stores and trace stores carry the nontemporal hint (launch.h)")
     a_("// STAB: stabilised central flux with face unknowns HF (Section 2.1)")
-    a_("template <typename R, bool ST, bool STAB>")
+    a_("// RATE: V is only written, V = sdt * rate (a rate into a buffer that is not cleared first)")
+    a_("template <typename R, bool ST, bool STAB, bool RATE>")
     a_(f"__global__ void {_launch_bounds(kp, nw, q)} {name}(const R* __restrict__ U, R* __restrict__ V,")
     a_("    const R* __restrict__ MU, const R* __restrict__ MV, const int* __restrict__ nbr,")
     a_("    const R* __restrict__ Tin, R* __restrict__ Tout, R sdt, R wall, int K,")
@@ -1261,6 +1262,7 @@ def emit_batch(p: int) -> str:
     a_("  const R wall = phase ? R(1) : R(-1);")
     a_("  const int K = sl.K;")
     a_("  constexpr bool STAB = false;  // batches use the central flux")
+    a_("  constexpr bool RATE = false;  // batches update their fields")
     a_("  R* const HF = nullptr;")
     a_("  const R* const SC = nullptr;")
     a_("  const R fdt = R(0);")
@@ -1296,14 +1298,18 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f'#include "phase_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_p{p}(const PhaseArgs<R>& a) {{",
-              "  if (a.HF && a.streaming)",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              "  if (a.overwrite && a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, false, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              "  else if (a.overwrite)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, false, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              "  else if (a.HF && a.streaming)",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  else if (a.HF)",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, true>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  else if (a.streaming)",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, true, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  else",
-              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
+              f"    hipLaunchKernelGGL((dgm_phase_p{p}<R, false, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.V, a.MU, a.MV, a.nbr, a.Tin, a.Tout, a.sdt, a.wall, a.K, a.HF, a.SC, a.fdt);",
               "  return hipGetLastError();",
               "}",
               f"hipError_t dgm_launch_phase_p{p}_f32(const PhaseArgs<float>& a) {{ return launch_p{p}<float>(a); }}"]
@@ -1397,13 +1403,13 @@ def _emit_mixed(outdir, p):
           "template <typename R>",
           f"static hipError_t launch_mix_p{p}(const PhaseArgs<R>& a, int dir) {{",
           "  if (dir == 0 && a.streaming)",
-          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, true, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
           "  else if (dir == 0)",
-          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          f"    hipLaunchKernelGGL((dgm_phase_eh_p{p}<R, false, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
           "  else if (a.streaming)",
-          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, true, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, true, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
           "  else",
-          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
+          f"    hipLaunchKernelGGL((dgm_phase_he_p{p}<R, false, false, false>), dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, {args});",
           "  return hipGetLastError();",
           "}",
           f"hipError_t dgm_launch_mix_p{p}_f32(const PhaseArgs<float>& a, int dir) {{ return launch_mix_p{p}<float>(a, dir); }}"]
