@@ -58,6 +58,14 @@ WORKLOAD = dict(workload="pec_cube_cavity_kuhn32_p6_fp32", cells=32, tets=196608
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_p6_cube32_traffic.json")
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """A line on stderr as each part of the run starts or ends (stdout carries the JSON line only)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def opcount(p):
     """Floating-point operations per element of one phase launch, as emitted by the
     generator (build step)."""
@@ -445,6 +453,7 @@ def main():
     E = torch.tensor(np.ascontiguousarray(E0), dtype=torch.float32, device="cuda").contiguous()
     H = torch.zeros_like(E)
     torch.cuda.synchronize()
+    progress("main leg: inputs ready, warm-up")
     W0, Q0 = m.energy(E, H, dt=dt)
     m.step(E, H, dt, a.warmup)
     stream = torch.cuda.current_stream()
@@ -507,6 +516,7 @@ def main():
     }
     # the config's full 500 steps at full size: drift of the leapfrog invariant (FP32 state,
     # FP64 reduction) over the whole run, after the timed region
+    progress(f"main leg: {a.steps} timed steps done ({phase_s * 1e6:.1f} us per phase)")
     rest = max(0, w.steps - steps_done)
     if rest:
         m.step(E, H, dt, rest)
@@ -516,23 +526,31 @@ def main():
     del E, H
     torch.cuda.empty_cache()
     if not a.no_stab:
+        progress("stabilized_flux leg")
         out["stabilized_flux"] = stab_leg(w, d, E0, a.stab_steps)
     if not a.no_mixed:
+        progress("mixed_orders leg")
         out["mixed_orders"] = mixed_leg(w, d, a.stab_steps)
     if not a.no_var:
+        progress("linear_material leg")
         out["linear_material"] = var_leg(w, d, E0, a.stab_steps)
     if not a.no_dense:
+        progress("dense_variant leg")
         out["dense_variant"] = dense_comparison(a.dense_steps)
     if not a.no_serve:
         from paper_1104_4208_amd import serve
 
-        rep = serve.serve_report(num=a.serve_requests, budget_gib=2.0, chunk=20, n_range=(4, a.serve_nmax))
+        progress("serving leg")
+        rep = serve.serve_report(num=a.serve_requests, budget_gib=2.0, chunk=20, n_range=(4, a.serve_nmax),
+                                  progress=True)
         rep["note"] = ("serving trace: Poisson arrivals at 50/s, n in 4..serve_nmax, p in 2..8, eps in {1,2,4}, "
                        "steps in 200..2000, jitter 0.1 h, 2 GiB admission budget, 20 steps per batched launch; "
                        "sequential = the same trace solved one request at a time with dgm_step")
         out["serving"] = rep
     if not a.no_cpu_baseline:
+        progress("cpu baseline and accuracy leg")
         out["cpu_baseline"], out["accuracy"] = oracle_leg(a.cpu_seconds, dense=not a.no_dense)
+    progress("done")
     print(json.dumps(out), flush=True)
 
 
