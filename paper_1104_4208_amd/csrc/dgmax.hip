@@ -566,6 +566,7 @@ int run_trace(dgm_mesh* m, const R* U, int fld, R* T, hipStream_t s) {
   TraceArgs<R> a;
   a.U = U;
   a.MU = Mdev<R>(m, fld);
+  a.nbr = m->d_nbr;
   a.T = T;
   a.K = (int)m->K;
   a.blocks = (int)((m->K + 63) / 64);

@@ -84,6 +84,7 @@ template <typename R>
 struct TraceArgs {
   const R* U;       // (3,N,K) stored-frame field
   const R* MU;      // (6,K) its conversion into the derivative frame
+  const int* nbr;   // (4,K) neighbour codes: x = 0 / y = 0 faces are stored only across tiles
   R* T;             // traces out (whole tiles)
   int K;
   int blocks;       // ceil(K / 64)

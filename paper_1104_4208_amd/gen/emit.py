@@ -1210,14 +1210,16 @@ def emit_phase(p: int, pU: int = None, pV: int = None, name: str = None) -> str:
 
 def emit_trace(p: int) -> str:
     """Trace kernel of order p: the traces of one field (the first phase of a run
-    and the rate operator need them before any phase has written them)."""
+    and the rate operator need them before any phase has written them).  Like the
+    phase kernels' trace stage it stores the x = 0 and y = 0 faces only where the
+    neighbour across them lies in another tile (inside a tile they pass through LDS)."""
     t, _, _, g, Lp, nw, pl = _kernel_setup(p)
     L = []
     a_ = L.append
     _header(a_, p, t, nw, pl, "trace kernel")
     a_("template <typename R>")
     a_(f"__global__ void {_launch_bounds(p, nw)} dgm_trace_p{p}(const R* __restrict__ U,")
-    a_("    const R* __restrict__ MU, R* __restrict__ Tout, int K)")
+    a_("    const R* __restrict__ MU, const int* __restrict__ nbr, R* __restrict__ Tout, int K)")
     a_("{")
     a_("  constexpr bool ST = false;")
     a_(f"  __shared__ R wl[{lds_words(p)}];")
@@ -1225,7 +1227,7 @@ def emit_trace(p: int) -> str:
     _elem_prologue(a_)
     _stage_field(a_, t, nw, "U", "MU")
     a_("  __syncthreads();")
-    _trace_stage(a_, t, g, pl, nw, masked=False)
+    _trace_stage(a_, t, g, pl, nw, masked=True)
     a_("}")
     return "\n".join(L) + "\n"
 
@@ -1323,7 +1325,7 @@ def emit_all(outdir: str, orders=range(1, TB.P_MAX + 1)):
               f'#include "trace_p{p}.inc"',
               "template <typename R>",
               f"static hipError_t launch_trace_p{p}(const TraceArgs<R>& a) {{",
-              f"  hipLaunchKernelGGL(dgm_trace_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.MU, a.T, a.K);",
+              f"  hipLaunchKernelGGL(dgm_trace_p{p}<R>, dim3(a.blocks), dim3({nw * LANES}), 0, a.stream, a.U, a.MU, a.nbr, a.T, a.K);",
               "  return hipGetLastError();",
               "}",
               f"hipError_t dgm_launch_trace_p{p}_f32(const TraceArgs<float>& a) {{ return launch_trace_p{p}<float>(a); }}"]
