@@ -897,7 +897,7 @@ int energy_var_core(dgm_mesh* m, const R* E, const R* H, const R* Hq, double out
   const bool cast = !std::is_same<T, R>::value;
   const size_t words = 5 * nmax + (cast ? nE + 2 * nH : 0);
   T* w = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&w), words * sizeof(T) + 8 * sizeof(double), s));
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&w), words * sizeof(T) + 5 * sizeof(double), s));
   T *y = w, *z = y + nmax, *r = z + nmax, *p = r + nmax, *t = p + nmax;
   const T *Et = reinterpret_cast<const T*>(E), *Ht = reinterpret_cast<const T*>(H), *Hqt = reinterpret_cast<const T*>(Hq);
   int rc = DGM_OK;
@@ -911,7 +911,9 @@ int energy_var_core(dgm_mesh* m, const R* E, const R* H, const R* Hq, double out
     Ht = c + nE;
     Hqt = c + nE + nH;
   }
-  double* d = reinterpret_cast<double*>(t + nmax + (cast ? nE + 2 * nH : 0));
+  // four FP64 scalars after the vectors, aligned to 8 bytes
+  double* d = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(t + nmax + (cast ? nE + 2 * nH : 0)) + 7) &
+                                        ~uintptr_t(7));
   const double tol = sizeof(T) == 8 ? 1e-13 : 1e-6;
   if (!rc) rc = mass_solve<T>(m, 0, Et, y, r, p, t, d, tol, s);
   if (!rc) rc = mass_solve<T>(m, 1, Ht, z, r, p, t, d, tol, s);
