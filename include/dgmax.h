@@ -121,6 +121,19 @@ int dgm_set_material(dgm_mesh* mesh, const double* eps, const double* mu);
  * DGM_ERR_MATERIAL, DGM_ERR_OOM, DGM_ERR_HIP. */
 int dgm_set_material_linear(dgm_mesh* mesh, const double* eps, const double* mu);
 
+/* The approximate mass inverse of dgm_set_material_linear alone (Section 3.3.2): for every
+ * component c and element, Y[c] = P X[c] with
+ *     (P r)_a = sum_x w_x phi_a(x) (sum_b phi_b(x) r_b) / m(x)
+ * on the reference element (the collapsed Gauss rule with p + 1 points per direction, weights
+ * summing to 1/6, m = eps for field 0 and mu for field 1, linear from the vertex values).
+ * For moments f_a = int_T f phi_a dx of a functional, P (f / |det F|) is the approximate
+ * inverse of the material-weighted mass matrix applied to them.  X and Y are device arrays
+ * of the field's shape (3, N, K) and dtype (N of that field's order), distinct; P acts on the
+ * mode index only, so any per-element frame of the components may be used.  One launch of
+ * the generated kernel dgm_mass_p{p}; asynchronous on the stream.  Errors: DGM_ERR_STATE
+ * without a linear material, DGM_ERR_ARG for a bad field or aliasing arrays. */
+int dgm_apply_mass_inverse(dgm_mesh* mesh, int dtype, int field, const void* X, void* Y, hipStream_t stream);
+
 /* Semi-discrete right-hand side (Section 2.1, eq. semidiscrete):
  *     dE = -M_eps^{-1} C^T H  (= eps^{-1} curl_h H),
  *     dH =  M_mu^{-1} C E     (= -mu^{-1} curl_h E),

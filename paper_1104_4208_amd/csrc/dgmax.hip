@@ -1518,6 +1518,16 @@ int dgm_set_material(dgm_mesh* m, const double* eps, const double* mu) {
   return rc;
 }
 
+int dgm_apply_mass_inverse(dgm_mesh* m, int dtype, int field, const void* X, void* Y, hipStream_t s) {
+  int rc = check_order(m, dtype);
+  if (rc) return rc;
+  if (!m->varmat) return fail(DGM_ERR_STATE, "no material linear on the elements (dgm_set_material_linear)");
+  if (field != 0 && field != 1) return fail(DGM_ERR_ARG, "field must be 0 (E, eps) or 1 (H, mu)");
+  if (!X || !Y || X == Y) return fail(DGM_ERR_ARG, "X and Y must be distinct device arrays");
+  if (dtype == DGM_F32) return run_mass<float>(m, (const float*)X, (float*)Y, field, 1.0, false, s);
+  return run_mass<double>(m, (const double*)X, (double*)Y, field, 1.0, false, s);
+}
+
 int dgm_set_material_linear(dgm_mesh* m, const double* eps, const double* mu) {
   if (!m) return fail(DGM_ERR_ARG, "null mesh");
   const size_t K = (size_t)m->K;

@@ -46,6 +46,7 @@ SIGNATURES = {
     "dgm_orders": (_c_i, [_c_p, _pi, _pi]),
     "dgm_set_material": (_c_i, [_c_p, _pd, _pd]),
     "dgm_set_material_linear": (_c_i, [_c_p, _pd, _pd]),
+    "dgm_apply_mass_inverse": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_p, _c_p]),
     "dgm_set_check_interval": (_c_i, [_c_p, _c_i64]),
     "dgm_apply_curl": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "dgm_step": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i64, _c_p]),
@@ -281,6 +282,20 @@ class Mesh:
             self._h, code, _ptr(E), _ptr(H), _ptr(dE if H is not None else None),
             _ptr(dH if E is not None else None), _stream()))
         return (dE if H is not None else None), (dH if E is not None else None)
+
+    def apply_mass_inverse(self, X, field: str = "E", out=None):
+        """dgm_apply_mass_inverse: out[c] = P X[c], the approximate mass inverse of the
+        material linear on the elements (field "E": eps, "H": mu)."""
+        torch = _torch()
+        if field not in ("E", "H"):
+            raise DGMError("field must be 'E' or 'H'")
+        X = self._field(X, field)
+        out = torch.empty_like(X) if out is None else self._field(out, field)
+        if out.dtype != X.dtype:
+            raise DGMError("X and out must share a dtype")
+        _check(load_library().dgm_apply_mass_inverse(self._h, _dtype_code(X), 0 if field == "E" else 1, _ptr(X),
+                                                      _ptr(out), _stream()))
+        return out
 
     def step(self, E, H, dt: float, nsteps: int = 1):
         E, H = self._field(E, "E"), self._field(H, "H")

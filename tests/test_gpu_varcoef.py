@@ -113,6 +113,34 @@ def test_var_apply_curl_parity(mesh, p, dtype):
     assert ee < tol and eh < tol
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_mass_inverse_alone(p, dtype):
+    """dgm_apply_mass_inverse: Y[c] = P X[c] for both fields against the oracle's approximate
+    inverse (which takes moments, so it is given X |det F|), on the ragged 162-tet mesh with
+    vertex values jumping between elements."""
+    if dtype == "f64" and p > P.max_order(P.DGM_F64):
+        pytest.skip("order not compiled for FP64")
+    rng = np.random.default_rng(800 + p)
+    verts, tets = synth.kuhn_mesh(3, 0.1, rng)
+    K = tets.shape[0]
+    eps_v, mu_v = rng.uniform(1, 4, (K, 4)), rng.uniform(0.5, 2, (K, 4))
+    pr = VarPair(verts, tets, p, eps_v, mu_v)
+    N = pr.s.N
+    X = rng.standard_normal((3, N, K))
+    Xo = np.transpose(X, (2, 1, 0))[:, pr.ipm, :]  # (K, N, 3) in the oracle's mode order
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    m = P.Mesh(verts, tets).set_order(p).set_material_linear(eps_v, mu_v)
+    for field in ("E", "H"):
+        Y = host(m.apply_mass_inverse(dev(X, tdt), field))
+        Yo = pr.s.approx_inverse(Xo * pr.s.absJ[:, None, None], field)
+        ref = np.transpose(Yo[:, pr.pm, :], (2, 1, 0))
+        err = rel_err(Y, ref)
+        print(f"mass inverse p={p} {dtype} {field}: {err:.2e}")
+        assert err < tol
+
+
 @pytest.mark.parametrize("p", [2, 5])
 def test_var_constant_values_equal_the_flat_method(p):
     """Vertex values equal on each element: the same rates as dgm_set_material (the
@@ -242,6 +270,8 @@ def test_var_full_size_sampled():
 def test_var_rejected_where_unsupported():
     verts, tets = synth.kuhn_mesh(1)
     m = P.Mesh(verts, tets).set_order(2)
+    with pytest.raises(P.DGMError, match="DGM_ERR_STATE"):
+        m.apply_mass_inverse(m.zeros(torch.float32))
     with pytest.raises(P.DGMError, match="DGM_ERR_MATERIAL"):
         m.set_material_linear(np.full((6, 4), -1.0))
     m.set_material_linear(np.full((6, 4), 2.0)).set_stab_alpha(1.0)
