@@ -239,6 +239,44 @@ def test_var_mixed_orders():
         assert ee < tol and eh < tol
 
 
+@pytest.mark.parametrize("pE,pH,qtol", [(3, 2, 1e-12), (8, 7, 1e-6)])
+def test_var_mixed_orders_run_and_invariant(pE, pH, qtol):
+    """Mixed orders with the material linear on the elements through the whole run path:
+    30 leapfrog steps (FP64 where the orders have FP64 kernels, else FP32) from random
+    fields; the invariant Q (energies by conjugate-gradient solves of the approximate mass
+    matrices, FP64 at (3, 2), FP32 at (8, 7) where no FP64 kernels exist) stays constant, and
+    at (3, 2) W and Q agree with the oracle's M~ products of the same state."""
+    rng = np.random.default_rng(81)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K = tets.shape[0]
+    eps_v, mu_v = smooth_material(verts, tets)
+    m = P.Mesh(verts, tets).set_orders(pE, pH).set_material_linear(eps_v, mu_v)
+    f64 = pE <= P.max_order(P.DGM_F64)
+    tdt = torch.float64 if f64 else torch.float32
+    E = dev(rng.standard_normal((3, P.num_modes(pE), K)), tdt)
+    H = dev(rng.standard_normal((3, P.num_modes(pH), K)), tdt)
+    dt, _ = m.estimate_dt(cfl=0.5, iters=30, seed=5)
+    W0, Q0 = m.energy(E, H, dt=dt)
+    if f64:
+        ts = sort_tets(tets)
+        mesh = oracle.build_mesh(verts, ts)
+        invE = VarMaterialSolver(mesh, pE, sorted_values(tets, eps_v), sorted_values(tets, mu_v))
+        invH = VarMaterialSolver(mesh, pH, sorted_values(tets, eps_v), sorted_values(tets, mu_v))
+        F = frames(verts, tets)
+        Finv = np.linalg.inv(F)
+        phys = lambda cov, p: np.einsum("kji,jmk->kmi", Finv, np.asarray(cov, float)[:, mode_perm(p)[1], :])
+        Eo, Ho = phys(host(E), pE), phys(host(H), pH)
+        Wo = 0.5 * invE.mass_dot(Eo, Eo, "E") + 0.5 * invH.mass_dot(Ho, Ho, "H")
+        assert abs(W0 - Wo) < 1e-10 * Wo
+    drift = 0.0
+    for _ in range(3):
+        m.step(E, H, dt, 10)
+        _, Q = m.energy(E, H, dt=dt)
+        drift = max(drift, abs(Q - Q0) / Q0)
+    print(f"var mixed ({pE},{pH}) {tdt}: Q drift over 30 steps {drift:.2e}")
+    assert drift < qtol
+
+
 def test_var_full_size_sampled():
     """The 32^3 x 6 jittered cube at p = 6 (196,608 tets), FP32, material linear on every
     element with eps jumping between 1 and 4 times a smooth factor: one application,
