@@ -22,15 +22,15 @@ component instead of the O(p^6) of a dense point matrix.
 
 Layout and parallelism: a workgroup takes one component of a tile of 64 elements (one
 per lane, so field loads and stores are coalesced as in the phase kernels) with one
-wave per a-slice of the points.  The slice index is uniform in a wave, so every
-per-slice coefficient (the C1 column, the slice's collapsed-coordinate factors) is a
-scalar load from constant memory, and the j- and c-steps have literal coefficients.
-The tile's input column is staged in LDS and read by every wave for the k-step; the
-LDS then holds each slice's result h_ij(a) of the steps back, and wave w finishes the
-rows r = w, w + q, ... by the k-step back over the q slices.  The Legendre c-step uses
-the mirror symmetry of the Gauss-Legendre nodes (even and odd degrees summed once for
-two nodes).  A lane holds about a hundred values, so several workgroups share a CU and
-their loads, arithmetic and stores overlap.
+wave per a-slice of the points.  The slice index is uniform in a wave, so the k-step and
+its transpose, whose coefficients depend on the slice, are literal code in a switch on it;
+the j- and c-steps have literal coefficients shared by all waves.  The tile's input column
+is staged in LDS and read by every wave for the k-step; the LDS then holds the slices'
+results h_ij(a) of the steps back, in sets of pairs (i, j) small enough for three
+workgroups per CU, and for each set the waves share its rows for the k-step back over
+the q slices.  The Legendre c-step uses the mirror symmetry of the Gauss-Legendre nodes
+(even and odd degrees summed once for two nodes).  A lane holds about eighty values at
+p = 6, so several workgroups share a CU and their loads, arithmetic and stores overlap.
 """
 from __future__ import annotations
 
@@ -67,8 +67,10 @@ def _column_cost(p, q):
 
 
 def mass_cost(p: int) -> dict:
-    """Floating-point operations per element (3 components) of one application, as emitted
-    (an FMA counts two; a reciprocal or add one)."""
+    """Floating-point operations per element (3 components) of one application: every
+    multiply-add of the k-, j- and c-steps and their transposes counts two, and so do the
+    adds of the even/odd split (a slight overcount); the point scale counts three per point
+    (material, reciprocal, product) and the column bases four per column."""
     t = TB.build(p)
     q = p + 1
     npairs = (p + 1) * (p + 2) // 2
