@@ -506,7 +506,7 @@ def main():
            "flops_per_dof_update": 2 * oc["with_traces"] / (6 * N),
            "achieved": flops_launch / phase_s / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
            "frac": flops_launch / phase_s / 1e12 / FP32_PEAK_TFLOPS,
-           "peak_note": "FP32 vector FMA without packed FP32 (switched off in this build): "
+           "peak_note": "FP32 vector FMA without packed FP32 (switched off by a compiler flag): "
                         "256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz",
            "count_note": "emitted multiplies and adds (FMA = 2) per element, including the x=0/y=0 trace "
                          f"jobs ({oc['trace_stage_recomputed_faces']} flops) that run only in tiles with an "
