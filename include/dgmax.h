@@ -7,7 +7,8 @@
  *     eps dE/dt =  curl H,   mu dH/dt = -curl E                  (Section 2)
  * discretised with piecewise polynomials of degree p in an L2-orthonormal
  * Dubiner basis (Sections 3.1 and 4.2.2), the covariant map (Section 3.2.1),
- * element-local mass inverses (Section 3.3.1) and the central flux
+ * element-local mass inverses (Section 3.3.1; for material linear inside the
+ * elements the approximate inverse of Section 3.3.2) and the central flux
  * (Section 2.1, eq. semidiscrete), advanced by symplectic Euler / leapfrog
  * with H updated first (Section 3).
  *
