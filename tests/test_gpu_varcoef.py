@@ -277,6 +277,27 @@ def test_var_mixed_orders_run_and_invariant(pE, pH, qtol):
     assert drift < qtol
 
 
+def test_var_probed_run_equals_plain_run():
+    """dgm_step_probe with the material linear on the elements leaves the same fields as
+    dgm_step (bitwise), and a longer probed run repeats the shorter one's signal."""
+    rng = np.random.default_rng(83)
+    verts, tets = synth.kuhn_mesh(2, 0.1, rng)
+    K = tets.shape[0]
+    eps_v, mu_v = smooth_material(verts, tets)
+    m = P.Mesh(verts, tets).set_order(3).set_material_linear(eps_v, mu_v)
+    N = P.num_modes(3)
+    E0 = dev(rng.standard_normal((3, N, K)), torch.float32)
+    H0 = dev(rng.standard_normal((3, N, K)), torch.float32)
+    w = dev(rng.standard_normal((3, N, K)), torch.float32)
+    Ea, Ha, Eb, Hb, Ec, Hc = E0.clone(), H0.clone(), E0.clone(), H0.clone(), E0.clone(), H0.clone()
+    m.step(Ea, Ha, 1e-3, 10)
+    s10 = m.step_probe(Eb, Hb, 1e-3, 10, w)
+    s20 = m.step_probe(Ec, Hc, 1e-3, 20, w)
+    torch.cuda.synchronize()
+    assert torch.equal(Ea, Eb) and torch.equal(Ha, Hb)
+    assert np.array_equal(s10, s20[:10]) and np.all(np.isfinite(s20))
+
+
 def test_var_full_size_sampled():
     """The 32^3 x 6 jittered cube at p = 6 (196,608 tets), FP32, material linear on every
     element with eps jumping between 1 and 4 times a smooth factor: one application,
