@@ -163,6 +163,8 @@ class Mesh:
                                    ctypes.byref(h)))
         self._h = h
         self.K = int(t.shape[0])
+        self._tets = t
+        self.nv = int(v.shape[0])
         self.p = None   # order of H (and of E unless set_orders gave E one more)
         self.pE = None
 
@@ -227,6 +229,20 @@ class Mesh:
         ma, mp = arr(mu)
         _check(load_library().dgm_set_material_linear(self._h, ep, mp))
         return self
+
+    def set_material_nodal(self, eps=None, mu=None):
+        """Material continuous and piecewise linear over the mesh: values at the mesh
+        vertices (length nv); each element takes those of its four vertices
+        (dgm_set_material_linear).  None means 1."""
+        def at_elements(x):
+            if x is None:
+                return None
+            a = np.asarray(x, dtype=np.float64)
+            if a.shape != (self.nv,):
+                raise DGMError(f"nodal material must have shape ({self.nv},)")
+            return a[self._tets]
+
+        return self.set_material_linear(at_elements(eps), at_elements(mu))
 
     def set_check_interval(self, every: int):
         """dgm_step checks the state every `every` steps (0: never) and raises

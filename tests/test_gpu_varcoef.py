@@ -277,6 +277,25 @@ def test_var_mixed_orders_run_and_invariant(pE, pH, qtol):
     assert drift < qtol
 
 
+def test_var_nodal_material_is_the_linear_one_at_the_vertices():
+    """set_material_nodal (values at the mesh vertices) gives the same rates, bitwise, as
+    set_material_linear with each element's vertex values, on a mesh with unsorted elements."""
+    rng = np.random.default_rng(85)
+    verts, tets = synth.two_tets(rng)
+    eps_n, mu_n = rng.uniform(1, 3, len(verts)), rng.uniform(1, 2, len(verts))
+    N = P.num_modes(4)
+    E = dev(rng.standard_normal((3, N, 2)), torch.float64)
+    H = dev(rng.standard_normal((3, N, 2)), torch.float64)
+    a = P.Mesh(verts, tets).set_order(4).set_material_nodal(eps_n, mu_n)
+    b = P.Mesh(verts, tets).set_order(4).set_material_linear(eps_n[tets], mu_n[tets])
+    dEa, dHa = a.apply_curl(E, H)
+    dEb, dHb = b.apply_curl(E, H)
+    torch.cuda.synchronize()
+    assert torch.equal(dEa, dEb) and torch.equal(dHa, dHb)
+    with pytest.raises(P.DGMError):
+        a.set_material_nodal(eps_n[:-1])
+
+
 def test_var_probed_run_equals_plain_run():
     """dgm_step_probe with the material linear on the elements leaves the same fields as
     dgm_step (bitwise), and a longer probed run repeats the shorter one's signal."""
