@@ -1,6 +1,6 @@
 """Write the run-length goldens of the FP32 workloads from the FP64 oracle.
 
-    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4 ...]
+    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4|cfg3_var ...]
 
 Calls only the oracle (and the shared seeded input generators in synth/): no
 value here comes from the HIP library.  Each workload's recipe (mesh kind,
@@ -28,6 +28,11 @@ Workload recipes (same seeds and draw order as the full-size workloads):
   cfg4  p = 8, eps = mu = 1, random physical modal coefficients N(0,1) for E
         (oracle mode order), H = 0, rescaled to W = 1 (seed 4), 200 steps,
         checkpoint every 20
+  cfg3_var  cfg3's mesh, draws and initial field with the material linear inside the
+        elements (Section 3.3.2, oracle/varcoef.py): eps at each element's vertices =
+        the element's eps in {1,4} times 1 + 0.25 sin(3x) cos(2z), mu = 1 + 0.2 y; eps
+        and mu are stored as (K,4) vertex values (sorted vertex order); W and Q are taken
+        with the approximate mass matrices
 The time step is 0.5 * 2 / sqrt(rho), rho from 40 oracle power iterations
 started from SplitMix64(seed).
 """
@@ -53,7 +58,16 @@ RECIPES = {
     "cfg2": dict(p=4, seed=2, jitter=0.0, eps=(1.0,), init="three_mode", steps=1000, every=100),
     "cfg3": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50),
     "cfg4": dict(p=8, seed=4, jitter=0.0, eps=(1.0,), init="random", steps=200, every=20),
+    "cfg3_var": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50, linear=True),
 }
+
+
+def linear_material(verts, tets, eps):
+    """Vertex values (K,4) of the linear-material recipe from the per-element draw."""
+    x = np.asarray(verts, float)[tets]
+    eps_v = eps[:, None] * (1.0 + 0.25 * np.sin(3.0 * x[..., 0]) * np.cos(2.0 * x[..., 2]))
+    mu_v = 1.0 + 0.2 * x[..., 1]
+    return eps_v, mu_v
 
 
 def setup(name):
@@ -66,7 +80,13 @@ def setup(name):
     K = tets.shape[0]
     eps = rng.choice(np.asarray(r["eps"]), size=K) if len(r["eps"]) > 1 else np.full(K, r["eps"][0])
     mu = np.ones(K)
-    s = oracle.Solver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
+    if r.get("linear"):
+        from oracle.varcoef import VarMaterialSolver
+
+        eps, mu = linear_material(verts, tets, eps)
+        s = VarMaterialSolver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
+    else:
+        s = oracle.Solver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
     if r["init"] == "three_mode":
         E = s.project(synth.three_mode_sum(rng).E)
     else:

@@ -317,6 +317,49 @@ def test_var_probed_run_equals_plain_run():
     assert np.array_equal(s10, s20[:10]) and np.all(np.isfinite(s20))
 
 
+def test_var_run_against_oracle_golden():
+    """The linear-material version of the p = 6 workload recipe (4^3 cells, jitter, eps in
+    {1,4} times a smooth factor, mu linear, three cavity modes) for its full 500 steps in
+    FP32 against the oracle's stored run (tests/golden/run_cfg3_var.npz, written by
+    make_run_goldens.py from the oracle alone): sampled elements at every checkpoint and the
+    whole final state within 1e-5 in the energy norm of the approximate mass matrices, and
+    the invariant Q within 1e-6 of the oracle's at every checkpoint."""
+    import importlib.util
+    import os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "golden", "run_cfg3_var.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    spec = importlib.util.spec_from_file_location("make_run_goldens", os.path.join(here, "golden", "make_run_goldens.py"))
+    MG = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(MG)
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    r, verts, tets, eps_v, mu_v, s, E, H = MG.setup("cfg3_var")
+    assert np.array_equal(verts, g["verts"]) and np.array_equal(tets, g["tets"])
+    assert np.array_equal(eps_v, g["eps"]) and np.array_equal(mu_v, g["mu"])
+    assert abs(float(E.sum()) - float(g["init_checksum"])) <= 1e-12 * max(1.0, abs(float(g["init_checksum"])))
+    pr = VarPair(verts, tets, r["p"], eps_v, mu_v)
+    dt, every, C = float(g["dt"]), int(g["every"]), int(g["steps"]) // int(g["every"])
+    m = P.Mesh(verts, tets).set_order(r["p"]).set_material_linear(eps_v, mu_v)
+    Eg, Hg = dev(pr.to_cov(E), torch.float32), dev(pr.to_cov(H), torch.float32)
+    smp = g["sample"]
+    worst_s = worst_q = 0.0
+    for c in range(C):
+        m.step(Eg, Hg, dt, every)
+        Ec, Hc = pr.to_phys(host(Eg)), pr.to_phys(host(Hg))
+        num = np.abs(Ec[smp] - g["E_s"][c]).max() + np.abs(Hc[smp] - g["H_s"][c]).max()
+        den = np.abs(g["E_s"][c]).max() + np.abs(g["H_s"][c]).max()
+        worst_s = max(worst_s, num / den)
+        _, Q = m.energy(Eg, Hg, dt=dt)
+        worst_q = max(worst_q, abs(Q - float(g["Q"][c])) / float(g["Q"][c]))
+    end = pr.s.rel_error(pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), g["E_end"], g["H_end"])
+    print(f"cfg3_var FP32 {int(g['steps'])} steps vs oracle: worst sampled {worst_s:.2e}, final energy-norm "
+          f"{end:.2e}, Q vs oracle {worst_q:.2e}")
+    assert worst_s < 1e-5 and end < 1e-5 and worst_q < 1e-6
+
+
 def test_var_full_size_sampled():
     """The 32^3 x 6 jittered cube at p = 6 (196,608 tets), FP32, material linear on every
     element with eps jumping between 1 and 4 times a smooth factor: one application,
