@@ -1,6 +1,6 @@
 """Write the run-length goldens of the FP32 workloads from the FP64 oracle.
 
-    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4|cfg3_var ...]
+    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4|cfg3_var|cfg3_stab ...]
 
 Calls only the oracle (and the shared seeded input generators in synth/): no
 value here comes from the HIP library.  Each workload's recipe (mesh kind,
@@ -33,6 +33,10 @@ Workload recipes (same seeds and draw order as the full-size workloads):
         the element's eps in {1,4} times 1 + 0.25 sin(3x) cos(2z), mu = 1 + 0.2 y; eps
         and mu are stored as (K,4) vertex values (sorted vertex order); W and Q are taken
         with the approximate mass matrices
+  cfg3_stab cfg3 with the stabilised central flux and face unknowns H^F (Section 2.1,
+        oracle/stab.py, alpha = p^2), H^F = 0 at the start; the time step from the
+        stabilised operator's power iteration; W and Q include the face term, and the
+        final face unknowns are stored as b_end (faces, NF, 3)
 The time step is 0.5 * 2 / sqrt(rho), rho from 40 oracle power iterations
 started from SplitMix64(seed).
 """
@@ -59,6 +63,7 @@ RECIPES = {
     "cfg3": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50),
     "cfg4": dict(p=8, seed=4, jitter=0.0, eps=(1.0,), init="random", steps=200, every=20),
     "cfg3_var": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50, linear=True),
+    "cfg3_stab": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50, stab=True),
 }
 
 
@@ -85,6 +90,10 @@ def setup(name):
 
         eps, mu = linear_material(verts, tets, eps)
         s = VarMaterialSolver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
+    elif r.get("stab"):
+        from oracle.stab import StabilizedSolver
+
+        s = StabilizedSolver(oracle.build_mesh(verts, tets), r["p"], eps, mu, alpha0=1.0)
     else:
         s = oracle.Solver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
     if r["init"] == "three_mode":
@@ -104,6 +113,8 @@ def sample_elements(K):
 
 def make(name):
     r, verts, tets, eps, mu, s, E, H = setup(name)
+    if r.get("stab"):
+        return make_stab(name, r, verts, tets, eps, mu, s, E, H)
     t0 = time.time()
     rho = s.spectral_radius(40, synth.splitmix64(r["seed"], E.size))
     dt = 1.0 / math.sqrt(rho)
@@ -126,6 +137,34 @@ def make(name):
     np.savez_compressed(out, verts=verts, tets=tets, eps=eps, mu=mu, dt=dt, steps=r["steps"], every=r["every"],
                         p=r["p"], seed=r["seed"], init_checksum=checksum, sample=smp, E_s=E_s, H_s=H_s, W=W, Q=Q,
                         E0W=W0, E_end=E, H_end=H)
+    print(f"{name}: wrote {out}", flush=True)
+
+
+def make_stab(name, r, verts, tets, eps, mu, s, E, H):
+    """The stabilised recipe: the same checkpoints, with the face unknowns in the state."""
+    t0 = time.time()
+    b = s.zeros_faces()
+    rho = s.spectral_radius_stab(40, synth.splitmix64(r["seed"], E.size))
+    dt = 1.0 / math.sqrt(rho)
+    smp = sample_elements(s.K)
+    C = r["steps"] // r["every"]
+    E_s = np.empty((C, len(smp), s.N, 3))
+    H_s = np.empty_like(E_s)
+    W = np.empty(C)
+    Q = np.empty(C)
+    checksum = float(E.sum())
+    W0 = s.energy_stab(E, H, b)
+    for c in range(C):
+        E, H, b = s.step_stab(E, H, b, dt, r["every"])
+        E_s[c], H_s[c] = E[smp], H[smp]
+        W[c] = s.energy_stab(E, H, b)
+        Q[c] = s.leapfrog_invariant_stab(E, H, b, dt)
+        print(f"{name}: step {(c + 1) * r['every']}/{r['steps']} W {W[c]:.15e} Q {Q[c]:.15e} "
+              f"({time.time() - t0:.0f} s)", flush=True)
+    out = os.path.join(HERE, f"run_{name}.npz")
+    np.savez_compressed(out, verts=verts, tets=tets, eps=eps, mu=mu, dt=dt, steps=r["steps"], every=r["every"],
+                        p=r["p"], seed=r["seed"], init_checksum=checksum, sample=smp, E_s=E_s, H_s=H_s, W=W, Q=Q,
+                        E0W=W0, E_end=E, H_end=H, b_end=b)
     print(f"{name}: wrote {out}", flush=True)
 
 

@@ -170,6 +170,53 @@ def test_step_stab_run_against_oracle(dtype, tol):
     assert s.face_dot(b, b) > 0
 
 
+def test_stab_run_against_oracle_golden():
+    """The p = 6 workload recipe (4^3 cells, jitter, eps in {1,4}, three cavity modes) with
+    the stabilised flux (alpha = p^2) for its full 500 steps in FP32 against the oracle's
+    stored run (tests/golden/run_cfg3_stab.npz, written by make_run_goldens.py from the
+    oracle alone): sampled elements at every checkpoint and the final (E, H, H^F) within
+    1e-5 in the stabilised energy norm, the invariant within 1e-6 of the oracle's."""
+    import importlib.util
+    import os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "golden", "run_cfg3_stab.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    spec = importlib.util.spec_from_file_location("make_run_goldens", os.path.join(here, "golden", "make_run_goldens.py"))
+    MG = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(MG)
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    r, verts, tets, eps, mu, s, E, H = MG.setup("cfg3_stab")
+    assert np.array_equal(verts, g["verts"]) and np.array_equal(tets, g["tets"]) and np.array_equal(eps, g["eps"])
+    assert abs(float(E.sum()) - float(g["init_checksum"])) <= 1e-12 * max(1.0, abs(float(g["init_checksum"])))
+    K = tets.shape[0]
+    pr = StabPair(verts, tets, r["p"], eps, mu)
+    m = P.Mesh(verts, tets).set_order(r["p"]).set_material(eps, mu).set_stab_alpha(1.0)
+    dt, every, C = float(g["dt"]), int(g["every"]), int(g["steps"]) // int(g["every"])
+    Eg, Hg = dev(pr.to_cov(E), torch.float32), dev(pr.to_cov(H), torch.float32)
+    HFg = dev(np.zeros((2, pr.NF, 4, K)), torch.float32)
+    smp = g["sample"]
+    worst_s = worst_q = 0.0
+    for c in range(C):
+        m.step_stab(Eg, Hg, HFg, dt, every)
+        Ec, Hc = pr.to_phys(host(Eg)), pr.to_phys(host(Hg))
+        num = np.abs(Ec[smp] - g["E_s"][c]).max() + np.abs(Hc[smp] - g["H_s"][c]).max()
+        den = np.abs(g["E_s"][c]).max() + np.abs(g["H_s"][c]).max()
+        worst_s = max(worst_s, num / den)
+        _, Q = m.energy_stab(Eg, Hg, HFg, dt=dt)
+        worst_q = max(worst_q, abs(Q - float(g["Q"][c])) / float(g["Q"][c]))
+    Eo, Ho, bo = pr.to_phys(host(Eg)), pr.to_phys(host(Hg)), pr.oracle_faces(host(HFg))
+    Ee, He, be = g["E_end"], g["H_end"], g["b_end"]
+    num = s.mass_dot(Eo - Ee, Eo - Ee, "E") + s.mass_dot(Ho - He, Ho - He, "H") + s.face_dot(bo - be, bo - be)
+    den = s.mass_dot(Ee, Ee, "E") + s.mass_dot(He, He, "H") + s.face_dot(be, be)
+    end = math.sqrt(num / den)
+    print(f"cfg3_stab FP32 {int(g['steps'])} steps vs oracle: worst sampled {worst_s:.2e}, final energy-norm "
+          f"{end:.2e}, Q vs oracle {worst_q:.2e}")
+    assert worst_s < 1e-5 and end < 1e-5 and worst_q < 1e-6
+
+
 def test_estimate_dt_stab_matches_oracle():
     """The power iteration approaches the largest eigenvalue of the stabilised
     second-order operator from below: within 1e-3 of the oracle's assembled value
