@@ -1,6 +1,6 @@
 """Write the run-length goldens of the FP32 workloads from the FP64 oracle.
 
-    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4|cfg3_var|cfg3_stab ...]
+    python tests/golden/make_run_goldens.py [cfg2|cfg3|cfg4|cfg3_var|cfg3_stab|cfg3_mixed ...]
 
 Calls only the oracle (and the shared seeded input generators in synth/): no
 value here comes from the HIP library.  Each workload's recipe (mesh kind,
@@ -37,6 +37,8 @@ Workload recipes (same seeds and draw order as the full-size workloads):
         oracle/stab.py, alpha = p^2), H^F = 0 at the start; the time step from the
         stabilised operator's power iteration; W and Q include the face term, and the
         final face unknowns are stored as b_end (faces, NF, 3)
+  cfg3_mixed cfg3 with mixed orders (Section 2, oracle/mixed.py): E of degree 7, H of
+        degree 6; the power iteration starts from an H-sized vector
 The time step is 0.5 * 2 / sqrt(rho), rho from 40 oracle power iterations
 started from SplitMix64(seed).
 """
@@ -64,6 +66,7 @@ RECIPES = {
     "cfg4": dict(p=8, seed=4, jitter=0.0, eps=(1.0,), init="random", steps=200, every=20),
     "cfg3_var": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50, linear=True),
     "cfg3_stab": dict(p=6, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50, stab=True),
+    "cfg3_mixed": dict(p=6, pE=7, seed=3, jitter=0.1, eps=(1.0, 4.0), init="three_mode", steps=500, every=50),
 }
 
 
@@ -90,6 +93,12 @@ def setup(name):
 
         eps, mu = linear_material(verts, tets, eps)
         s = VarMaterialSolver(oracle.build_mesh(verts, tets), r["p"], eps, mu)
+    elif r.get("pE"):
+        from oracle.mixed import MixedSolver
+
+        s = MixedSolver(oracle.build_mesh(verts, tets), r["pE"], r["p"], eps, mu)
+        E = s.project(synth.three_mode_sum(rng).E, "E")
+        return r, verts, tets, eps, mu, s, E, np.zeros((K, s.NH, 3))
     elif r.get("stab"):
         from oracle.stab import StabilizedSolver
 
@@ -116,12 +125,12 @@ def make(name):
     if r.get("stab"):
         return make_stab(name, r, verts, tets, eps, mu, s, E, H)
     t0 = time.time()
-    rho = s.spectral_radius(40, synth.splitmix64(r["seed"], E.size))
+    rho = s.spectral_radius(40, synth.splitmix64(r["seed"], H.size if r.get("pE") else E.size))
     dt = 1.0 / math.sqrt(rho)
     smp = sample_elements(s.K)
     C = r["steps"] // r["every"]
-    E_s = np.empty((C, len(smp), s.N, 3))
-    H_s = np.empty_like(E_s)
+    E_s = np.empty((C, len(smp), E.shape[1], 3))
+    H_s = np.empty((C, len(smp), H.shape[1], 3))
     W = np.empty(C)
     Q = np.empty(C)
     checksum = float(E.sum())

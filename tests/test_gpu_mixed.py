@@ -116,6 +116,48 @@ def test_mixed_run_against_oracle(dtype, tol):
     assert drift < (1e-12 if dtype == torch.float64 else 1e-6)
 
 
+def test_mixed_run_against_oracle_golden():
+    """The p = 6 workload recipe (4^3 cells, jitter, eps in {1,4}, three cavity modes) with E
+    of degree 7 and H of degree 6 for its full 500 steps in FP32 against the oracle's stored
+    run (tests/golden/run_cfg3_mixed.npz, written by make_run_goldens.py from the oracle
+    alone): sampled elements at every checkpoint and the final state within 1e-5 in the
+    energy norm, the invariant within 1e-6 of the oracle's."""
+    import importlib.util
+    import os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "golden", "run_cfg3_mixed.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    spec = importlib.util.spec_from_file_location("make_run_goldens", os.path.join(here, "golden", "make_run_goldens.py"))
+    MG = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(MG)
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    r, verts, tets, eps, mu, s, E, H = MG.setup("cfg3_mixed")
+    assert np.array_equal(verts, g["verts"]) and np.array_equal(tets, g["tets"]) and np.array_equal(eps, g["eps"])
+    assert abs(float(E.sum()) - float(g["init_checksum"])) <= 1e-12 * max(1.0, abs(float(g["init_checksum"])))
+    pE, pH = r["pE"], r["p"]
+    pr = MixedPair(verts, tets, pE, pH, eps, mu)
+    m = P.Mesh(verts, tets).set_orders(pE, pH).set_material(eps, mu)
+    dt, every, C = float(g["dt"]), int(g["every"]), int(g["steps"]) // int(g["every"])
+    Eg, Hg = dev(pr.to_cov(E, pE), torch.float32), dev(pr.to_cov(H, pH), torch.float32)
+    smp = g["sample"]
+    worst_s = worst_q = 0.0
+    for c in range(C):
+        m.step(Eg, Hg, dt, every)
+        Ec, Hc = pr.to_phys(host(Eg), pE), pr.to_phys(host(Hg), pH)
+        num = np.abs(Ec[smp] - g["E_s"][c]).max() + np.abs(Hc[smp] - g["H_s"][c]).max()
+        den = np.abs(g["E_s"][c]).max() + np.abs(g["H_s"][c]).max()
+        worst_s = max(worst_s, num / den)
+        _, Q = m.energy(Eg, Hg, dt=dt)
+        worst_q = max(worst_q, abs(Q - float(g["Q"][c])) / float(g["Q"][c]))
+    end = pr.s.rel_error(pr.to_phys(host(Eg), pE), pr.to_phys(host(Hg), pH), g["E_end"], g["H_end"])
+    print(f"cfg3_mixed FP32 {int(g['steps'])} steps vs oracle: worst sampled {worst_s:.2e}, final energy-norm "
+          f"{end:.2e}, Q vs oracle {worst_q:.2e}")
+    assert worst_s < 1e-5 and end < 1e-5 and worst_q < 1e-6
+
+
 def test_mixed_estimate_dt_and_spectrum():
     """The power iteration approaches the largest eigenvalue of the mixed operator from
     below (within 1e-3 of the oracle's assembled value after 200 iterations)."""
