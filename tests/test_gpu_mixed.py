@@ -67,8 +67,6 @@ def test_mixed_apply_curl_parity(mesh, pH, dtype):
     pE = pH + 1
     if dtype == "f64" and pE > P.max_order(P.DGM_F64):
         pytest.skip("order not compiled for FP64")
-    if pH >= 4 and mesh == "jit3_ragged":
-        pytest.skip("covered at lower orders; keeps the oracle fast")
     rng = np.random.default_rng(500 + pH)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]

@@ -47,8 +47,6 @@ def _materials(rng, K):
 def test_apply_curl_parity(mesh, p, dtype):
     if dtype == "f64" and p > P.max_order(P.DGM_F64):
         pytest.skip("order not compiled for FP64")
-    if p >= 5 and mesh in ("jit3_ragged",):
-        pytest.skip("covered at lower orders; keeps the oracle fast")
     rng = np.random.default_rng(100 + p)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]

@@ -108,8 +108,6 @@ def owner_mask(pr):
 def test_apply_stab_parity(mesh, p, dtype):
     if dtype == "f64" and p > P.max_order(P.DGM_F64):
         pytest.skip("order not compiled for FP64")
-    if p >= 5 and mesh == "jit3_ragged":
-        pytest.skip("covered at lower orders; keeps the oracle fast")
     rng, pr, m = _mesh(mesh, p, dtype, 300 + p)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     tol = 1e-10 if dtype == "f64" else 1e-5

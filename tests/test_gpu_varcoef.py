@@ -94,8 +94,6 @@ def smooth_material(verts, tets):
 def test_var_apply_curl_parity(mesh, p, dtype):
     if dtype == "f64" and p > P.max_order(P.DGM_F64):
         pytest.skip("order not compiled for FP64")
-    if p >= 5 and mesh == "jit3_ragged":
-        pytest.skip("covered at lower orders; keeps the oracle fast")
     rng = np.random.default_rng(700 + p)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]
