@@ -16,6 +16,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1104_4208_amd as P  # noqa: E402
+from paper_1104_4208_amd.gen.emit import F64_MAX_ORDER as F64_MAX  # noqa: E402
+from paper_1104_4208_amd.gen.tables import P_MAX  # noqa: E402
+
+# every order in FP32, the orders instantiated in FP64
+ORDERS_DTYPES = [(p, "f32") for p in range(1, P_MAX + 1)] + [(p, "f64") for p in range(1, F64_MAX + 1)]
 
 
 class MixedPair:
@@ -60,13 +65,10 @@ MESHES = {
 }
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("pH", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("pH,dtype", [(p, "f32") for p in range(1, P_MAX)] + [(p, "f64") for p in range(1, F64_MAX)])
 @pytest.mark.parametrize("mesh", list(MESHES))
 def test_mixed_apply_curl_parity(mesh, pH, dtype):
     pE = pH + 1
-    if dtype == "f64" and pE > P.max_order(P.DGM_F64):
-        pytest.skip("order not compiled for FP64")
     rng = np.random.default_rng(500 + pH)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]

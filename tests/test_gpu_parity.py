@@ -17,6 +17,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1104_4208_amd as P  # noqa: E402
+from paper_1104_4208_amd.gen.emit import F64_MAX_ORDER as F64_MAX  # noqa: E402
+from paper_1104_4208_amd.gen.tables import P_MAX  # noqa: E402
+
+# every order in FP32, the orders instantiated in FP64
+ORDERS_DTYPES = [(p, "f32") for p in range(1, P_MAX + 1)] + [(p, "f64") for p in range(1, F64_MAX + 1)]
 
 
 def dev(a, dtype):
@@ -41,12 +46,9 @@ def _materials(rng, K):
     return rng.uniform(1.0, 4.0, K), rng.uniform(1.0, 2.0, K)
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("p,dtype", ORDERS_DTYPES)
 @pytest.mark.parametrize("mesh", list(MESHES))
 def test_apply_curl_parity(mesh, p, dtype):
-    if dtype == "f64" and p > P.max_order(P.DGM_F64):
-        pytest.skip("order not compiled for FP64")
     rng = np.random.default_rng(100 + p)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]

@@ -25,6 +25,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1104_4208_amd as P  # noqa: E402
+from paper_1104_4208_amd.gen.emit import F64_MAX_ORDER as F64_MAX  # noqa: E402
+from paper_1104_4208_amd.gen.tables import P_MAX  # noqa: E402
+
+# every order in FP32, the orders instantiated in FP64
+ORDERS_DTYPES = [(p, "f32") for p in range(1, P_MAX + 1)] + [(p, "f64") for p in range(1, F64_MAX + 1)]
 
 ALPHA0 = 1.0
 
@@ -102,12 +107,9 @@ def owner_mask(pr):
     return mask
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("p,dtype", ORDERS_DTYPES)
 @pytest.mark.parametrize("mesh", list(MESHES))
 def test_apply_stab_parity(mesh, p, dtype):
-    if dtype == "f64" and p > P.max_order(P.DGM_F64):
-        pytest.skip("order not compiled for FP64")
     rng, pr, m = _mesh(mesh, p, dtype, 300 + p)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     tol = 1e-10 if dtype == "f64" else 1e-5

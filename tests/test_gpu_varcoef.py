@@ -24,6 +24,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1104_4208_amd as P  # noqa: E402
+from paper_1104_4208_amd.gen.emit import F64_MAX_ORDER as F64_MAX  # noqa: E402
+from paper_1104_4208_amd.gen.tables import P_MAX  # noqa: E402
+
+# every order in FP32, the orders instantiated in FP64
+ORDERS_DTYPES = [(p, "f32") for p in range(1, P_MAX + 1)] + [(p, "f64") for p in range(1, F64_MAX + 1)]
 
 
 def sorted_values(tets, vals):
@@ -88,12 +93,9 @@ def smooth_material(verts, tets):
     return eps, mu
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("p,dtype", ORDERS_DTYPES)
 @pytest.mark.parametrize("mesh", list(MESHES))
 def test_var_apply_curl_parity(mesh, p, dtype):
-    if dtype == "f64" and p > P.max_order(P.DGM_F64):
-        pytest.skip("order not compiled for FP64")
     rng = np.random.default_rng(700 + p)
     verts, tets = MESHES[mesh](rng)
     K = tets.shape[0]
@@ -111,14 +113,11 @@ def test_var_apply_curl_parity(mesh, p, dtype):
     assert ee < tol and eh < tol
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("p,dtype", ORDERS_DTYPES)
 def test_mass_inverse_alone(p, dtype):
     """dgm_apply_mass_inverse: Y[c] = P X[c] for both fields against the oracle's approximate
     inverse (which takes moments, so it is given X |det F|), on the ragged 162-tet mesh with
     vertex values jumping between elements."""
-    if dtype == "f64" and p > P.max_order(P.DGM_F64):
-        pytest.skip("order not compiled for FP64")
     rng = np.random.default_rng(800 + p)
     verts, tets = synth.kuhn_mesh(3, 0.1, rng)
     K = tets.shape[0]
